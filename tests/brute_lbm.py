@@ -1,0 +1,125 @@
+"""Independent brute-force single step of the lattice-BGK update (numpy).
+
+Used only to pin the C oracle.  Written separately from it and in a different
+style:
+  * push streaming: every departing population is moved along its velocity
+    and, if its path ends inside the wall or body, reflected by tracing
+    where the bounced particle lands (the C oracle pulls instead);
+  * the collision builds the Hermite basis H0, H1, H2 explicitly and
+    projects the non-equilibrium part onto H2 with einsum (Sec. 5, eqs.
+    feq_h2, fne, regularization).
+Geometry conventions: half-way walls; plate wall at y = -1/2 moving with
+U_w along x, x periodic, a stationary wall at y = ny - 1/2 or an open
+rest-equilibrium far field; box = solid cells [x0,x0+lx) x [y0,y0+ly).
+"""
+import numpy as np
+
+
+def _reflect_box(p, d, box):
+    """Arrival cell of a population leaving fluid cell p whose straight
+    destination d is solid.  Per axis: a departure coordinate outside the
+    body's range is mirrored through the face plane, else kept."""
+    x0, y0, lx, ly = box
+    lo = (x0, y0)
+    hi = (x0 + lx, y0 + ly)
+    a = []
+    for k in range(2):
+        if p[k] < lo[k]:
+            a.append(2 * lo[k] - 1 - d[k])
+        elif p[k] >= hi[k]:
+            a.append(2 * hi[k] - 1 - d[k])
+        else:
+            a.append(p[k])
+    return tuple(a)
+
+
+def stream(f, v, w, theta, geometry, far, box, U, rho0):
+    """Push streaming.  Returns (f_adv, Fx, Fy); f is [q][y][x]."""
+    Q, ny, nx = f.shape
+    opp = [int(np.flatnonzero((v[:, 0] == -v[i, 0]) & (v[:, 1] == -v[i, 1]))[0]) for i in range(Q)]
+    fadv = np.full_like(f, np.nan)
+    Fx = Fy = 0.0
+
+    def solid(x, y):
+        if geometry != "box":
+            return False
+        x0, y0, lx, ly = box
+        return x0 <= x < x0 + lx and y0 <= y < y0 + ly
+
+    for q in range(Q):
+        ux, uy = int(v[q, 0]), int(v[q, 1])
+        for y in range(ny):
+            for x in range(nx):
+                if solid(x, y):
+                    continue
+                val = f[q, y, x]
+                dx, dy = x + ux, y + uy
+                if geometry == "plate":
+                    dx %= nx
+                    if dy < 0:
+                        # bounces on the moving wall; arrives with velocity -u
+                        i = opp[q]
+                        ax, ay = x, -1 - dy
+                        out = val + 2 * w[i] * rho0 * (v[i, 0] * U) / theta
+                        fadv[i, ay, ax] = out
+                        Fx += -v[i, 0] * (val + out)
+                        Fy += -v[i, 1] * (val + out)
+                        continue
+                    if dy >= ny:
+                        if far == "wall":
+                            fadv[opp[q], 2 * ny - 1 - dy, x] = val
+                        continue
+                    fadv[q, dy, dx] = val
+                elif geometry == "periodic":
+                    fadv[q, dy % ny, dx % nx] = val
+                else:
+                    if not (0 <= dx < nx and 0 <= dy < ny):
+                        continue
+                    if solid(dx, dy):
+                        i = opp[q]
+                        ax, ay = _reflect_box((x, y), (dx, dy), box)
+                        out = val + 2 * w[i] * rho0 * (v[i, 0] * U) / theta
+                        fadv[i, ay, ax] = out
+                        Fx += -v[i, 0] * (val + out)
+                        Fy += -v[i, 1] * (val + out)
+                        continue
+                    fadv[q, dy, dx] = val
+    # whatever was not delivered comes from the rest-equilibrium far field
+    hole = np.isnan(fadv)
+    fadv[hole] = (w[:, None, None] * rho0 * np.ones_like(f))[hole]
+    if geometry == "box":
+        x0, y0, lx, ly = box
+        fadv[:, y0:y0 + ly, x0:x0 + lx] = 0.0
+    return fadv, Fx, Fy
+
+
+def collide(fadv, v, w, theta, tau, regularized=True):
+    """Collision on a [q][y][x] field with the explicit Hermite basis."""
+    vv = v.astype(np.float64)
+    H1 = vv                                             # [Q,2]
+    H2 = vv[:, :, None] * vv[:, None, :] - theta * np.eye(2)[None]  # [Q,2,2]
+    rho = fadv.sum(0)
+    j = np.einsum("qyx,qa->ayx", fadv, vv)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        u = np.where(rho != 0, j / np.where(rho != 0, rho, 1), 0.0)
+    # equilibrium, eq. feq_h2, written as a Hermite expansion
+    a1 = rho * u                                        # [2,y,x]
+    a2 = rho[None, None] * u[:, None] * u[None, :]      # [2,2,y,x]
+    feq = w[:, None, None] * (rho[None]
+                              + np.einsum("qa,ayx->qyx", H1, a1) / theta
+                              + np.einsum("qab,abyx->qyx", H2, a2) / (2 * theta ** 2))
+    keep = 1.0 - (0.0 if np.isinf(tau) else 1.0 / tau)
+    if not regularized:
+        return feq + keep * (fadv - feq)
+    A = np.einsum("qyx,qa,qb->abyx", fadv - feq, vv, vv)
+    fne = w[:, None, None] * np.einsum("qab,abyx->qyx", H2, A) / (2 * theta ** 2)
+    return feq + keep * fne
+
+
+def step(f, v, w, theta, tau, geometry, far, box, U, rho0=1.0, regularized=True):
+    fadv, Fx, Fy = stream(f, v, w, theta, geometry, far, box, U, rho0)
+    out = collide(fadv, v, w, theta, tau, regularized)
+    if geometry == "box":
+        x0, y0, lx, ly = box
+        out[:, y0:y0 + ly, x0:x0 + lx] = 0.0
+    return out, Fx, Fy
