@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the lattice-BGK hot path on one MI355X.
+
+Default workload (beam_box): the 1024 x 1024 domain with a 32 x 16 body
+oscillating along x, D2Q37, FP32 deviation storage with FP64 force and
+lock-in, at tau*omega = 0.1, 1 and 10.  The three solves run as one batch:
+one step = one fused stream-collide launch over all three lattices (pull
+advection, bounce-back with the moving-wall term, moments, H2 equilibrium,
+regularized collision, FP64 momentum-exchange partial sums) plus one launch
+that reduces the force of each solve, appends it to the history and
+accumulates the lock-in sums.  Inputs are resident in HBM before timing.
+
+Prints one JSON line: MLUPS (fluid-cell updates per second), the dominant
+kernel's achieved algorithmic bandwidth against the 8 TB/s HBM peak (HIP
+events around every launch of the fused kernel in the timed region), and the
+CPU oracle timed on a bounded sample on this host.
+
+    python bench.py [--steps K] [--warmup W] [--workload beam_box|plate_sweep]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS & HBM GB/s (%peak); sweep solves/s + p50/p99 latency vs plain loop")
+HBM_PEAK_GBS = 8000.0
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "step_kernel_beam_box_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_0904_4504_amd", "csrc", "kernels.hip")
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def workload(name, steps, warmup):
+    import lbm_inputs as W
+    n = warmup + steps
+    if name == "beam_box":
+        solves = [W.beam_box(tw) for tw in W.BEAM_TAU_OMEGA]
+        desc = ("beam_box: 1024x1024 domain, 32x16 body centred, rest-equilibrium far field, "
+                "D2Q37 FP32-deviation storage, FP64 force + lock-in, tau*omega {0.1, 1, 10} "
+                "as one batch")
+    elif name == "plate_sweep":
+        solves = [W.plate_sweep(tw) for tw in W.PLATE_SWEEP_TAU_OMEGA]
+        desc = ("plate_sweep: 4x2048 plates, stationary far wall, D2Q37 FP32-deviation, "
+                "tau*omega {0.01, 0.1, 1, 10, 100} as one batch")
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    # the timed steps form the lock-in window, so every step runs the whole path
+    solves = [s.scaled(n, steps) for s in solves]
+    return solves, desc
+
+
+def traffic_from_profile(launch_bytes_alg):
+    """HBM bytes per launch from committed rocprofv3 counters, if they were
+    taken on the current kernel source; else None."""
+    try:
+        with open(PROFILE_COUNTERS) as fh:
+            prof = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return prof.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(solve, budget_s):
+    """The FP64 oracle on this host's cores on a bounded sample of the workload."""
+    import oracle as O
+    import lbm_inputs as W
+    cores = len(os.sched_getaffinity(0))
+    p = O.OracleParams(
+        Q=solve.Q, nx=solve.nx, ny=solve.ny, tau=solve.tau, omega=solve.omega, u0=solve.u0,
+        geometry=O.GEOM_BOX if solve.geometry == W.BOX else O.GEOM_PLATE,
+        far=O.FAR_EQ if solve.far == W.FAR_EQ else O.FAR_WALL,
+        box_x0=solve.box[0], box_y0=solve.box[1], box_lx=solve.box[2], box_ly=solve.box[3],
+        nthreads=cores)
+    t0 = time.perf_counter()
+    O.run(p, 2)
+    per_step = (time.perf_counter() - t0) / 2
+    nsteps = max(2, min(400, int(budget_s / max(per_step, 1e-6))))
+    t0 = time.perf_counter()
+    O.run(p, nsteps)
+    dt = time.perf_counter() - t0
+    mlups = solve.fluid_cells * nsteps / dt / 1e6
+    return {"value": mlups, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{solve.name}: {nsteps} steps of one {solve.nx}x{solve.ny} lattice from "
+                      f"rest, FP64 oracle, OpenMP over rows on {cores} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="beam_box")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the solves of a sweep are independent and would "
+              "be split across GPUs by solve, which this build does not do; use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_0904_4504_amd as P
+
+    torch.cuda.set_device(0)
+    solves, desc = workload(a.workload, a.steps, a.warmup)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        solvers = [P.Solver(P.params_from_solve(s), stream=stream) for s in solves]
+        batch = P.Batch(stream)
+        for sv in solvers:
+            batch.add(sv)
+        batch.step(a.warmup)
+        batch.synchronize()
+        batch.timing(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        batch.step(a.steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        batch.synchronize()
+        elapsed_ms = t0.elapsed_time(t1)
+        kern_ms, launches = batch.kernel_time()
+        z = [sv.impedance() for sv in solvers]
+        batch.close()
+        for sv in solvers:
+            sv.close()
+
+    cells = sum(s.fluid_cells for s in solves)
+    Q = solves[0].Q
+    bytes_per_lu = 2 * Q * 4
+    mlups = cells * a.steps / (elapsed_ms / 1e3) / 1e6
+    avg_kernel_s = kern_ms / 1e3 / launches
+    launch_bytes = bytes_per_lu * cells
+    achieved = launch_bytes / avg_kernel_s / 1e9
+    traffic = traffic_from_profile(launch_bytes)
+    out = {
+        "metric": METRIC,
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed_ms / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "lattice": f"D2Q{Q}",
+            "solves": len(solves),
+            "fluid_cells": cells,
+            "algorithmic_bytes_per_update": bytes_per_lu,
+            "force_and_lockin": "f64",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "lbm::step_kernel<D2Q37, float, false>",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "avg_kernel_ms": avg_kernel_s * 1e3,
+            "launches": launches,
+        },
+        "impedance": [{"tau_omega": s.tau_omega, "R": zz["R"], "X": zz["X"]}
+                      for s, zz in zip(solves, z)],
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(solves[len(solves) // 2].scaled(2, 0), a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,565 @@
+// C ABI of the solver: validation, device memory layout, lifecycle, the
+// per-step launch sequence, and host-side read-out (force history, lock-in
+// fit, populations).  See include/lbm.h for the contract of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+template <class L>
+void fill_lattice(HostLattice* h) {
+  h->Q = L::Q;
+  h->R = L::R;
+  for (int i = 0; i < L::Q; ++i) {
+    h->vx.push_back(L::vx[i]);
+    h->vy.push_back(L::vy[i]);
+    h->orbit.push_back(L::orbit[i]);
+    h->opp.push_back(opposite<L>(i));
+  }
+}
+
+bool host_lattice(int Q, HostLattice* h) {
+  if (Q == 9) fill_lattice<D2Q9>(h);
+  else if (Q == 37) fill_lattice<D2Q37>(h);
+  else return false;
+  return lattice_weights(Q, &h->lw);
+}
+
+int validate(const lbm_params* p, HostLattice* lat) {
+  if (!p) return LBM_EINVAL;
+  if (p->abi_version != LBM_ABI_VERSION) return LBM_EABI;
+  if (!host_lattice((int)p->lattice, lat)) return LBM_EINVAL;
+  if (p->storage != LBM_STORE_F64 && p->storage != LBM_STORE_F32_DEV) return LBM_EINVAL;
+  if (p->collision != LBM_COLL_REGULARIZED && p->collision != LBM_COLL_BGK) return LBM_EINVAL;
+  if (p->wall != LBM_WALL_BB) return LBM_EINVAL;
+  if (p->far != LBM_FAR_WALL && p->far != LBM_FAR_EQ) return LBM_EINVAL;
+  const int R = lat->R;
+  if (p->nx < std::max(3, R) || p->ny < std::max(3, R)) return LBM_EINVAL;
+  if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) return LBM_EINVAL;
+  if (!(p->tau > 0.5)) return LBM_EINVAL;  // rejects NaN too; +inf allowed
+  if (!std::isfinite(p->omega) || !std::isfinite(p->u0)) return LBM_EINVAL;
+  if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return LBM_EINVAL;
+  if (p->max_steps < 1 || p->max_steps > ((int64_t)1 << 32)) return LBM_EINVAL;
+  if (p->lockin_first < 0 || p->lockin_count < 0 ||
+      p->lockin_first + p->lockin_count > p->max_steps)
+    return LBM_EINVAL;
+  if (p->history_capacity < 0 || p->history_capacity > p->max_steps) return LBM_EINVAL;
+  switch (p->geometry) {
+    case LBM_GEOM_PLATE:
+    case LBM_GEOM_PERIODIC:
+      break;
+    case LBM_GEOM_BOX:
+      if (p->far != LBM_FAR_EQ) return LBM_EINVAL;
+      if (p->box_lx < R || p->box_ly < R || p->box_x0 < R || p->box_y0 < R) return LBM_EINVAL;
+      if ((int64_t)p->box_x0 + p->box_lx + R > p->nx ||
+          (int64_t)p->box_y0 + p->box_ly + R > p->ny)
+        return LBM_EINVAL;
+      break;
+    default:
+      return LBM_EINVAL;
+  }
+  return LBM_OK;
+}
+
+bool in_body(const lbm_params* p, int x, int y) {
+  return p->geometry == LBM_GEOM_BOX && x >= p->box_x0 && x < p->box_x0 + p->box_lx &&
+         y >= p->box_y0 && y < p->box_y0 + p->box_ly;
+}
+
+// True if a population arriving at fluid cell (x, y) along q comes from the
+// moving wall or body (a bounce-back link that carries force).
+bool is_link(const lbm_params* p, const HostLattice& L, int x, int y, int q) {
+  const int sx = x - L.vx[q], sy = y - L.vy[q];
+  if (p->geometry == LBM_GEOM_PLATE) return sy < 0;
+  if (p->geometry == LBM_GEOM_BOX) return in_body(p, sx, sy);
+  return false;
+}
+
+// Tile -> partial slot table, and the rest-state part of the wall force
+// -sum_links 2 v_i w_i rho0 (exact link enumeration, long double).
+void plan_links(const lbm_params* p, const HostLattice& L, const Layout& lay,
+                std::vector<int32_t>* slot, int32_t* nslots, double fstatic[2]) {
+  slot->assign(lay.ntiles, -1);
+  long double sx = 0, sy = 0;
+  int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+  if (p->geometry == LBM_GEOM_PLATE) {
+    x0 = 0; x1 = p->nx; y0 = 0; y1 = std::min(L.R, p->ny);
+  } else if (p->geometry == LBM_GEOM_BOX) {
+    x0 = p->box_x0 - L.R; x1 = p->box_x0 + p->box_lx + L.R;
+    y0 = p->box_y0 - L.R; y1 = p->box_y0 + p->box_ly + L.R;
+  }
+  for (int y = y0; y < y1; ++y)
+    for (int x = x0; x < x1; ++x) {
+      if (in_body(p, x, y)) continue;
+      bool any = false;
+      for (int q = 0; q < L.Q; ++q)
+        if (is_link(p, L, x, y, q)) {
+          any = true;
+          const long double m = 2.0L * L.lw.w_orbit_ld[L.orbit[q]] * (long double)p->rho0;
+          sx -= L.vx[q] * m;
+          sy -= L.vy[q] * m;
+        }
+      if (any) (*slot)[((int64_t)y * p->nx + x) / lay.cells_per_tile] = 0;
+    }
+  int32_t n = 0;
+  for (auto& s : *slot)
+    if (s >= 0) s = n++;
+  *nslots = n;
+  fstatic[0] = (double)sx;
+  fstatic[1] = (double)sy;
+}
+
+void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
+  const uint64_t es = p->storage == LBM_STORE_F64 ? 8 : 4;
+  lay->pitch = p->nx >= 64 ? (int64_t)align_up(p->nx, 64) : p->nx;
+  // planes start 256 elements past a 256-element boundary apart, so that the
+  // Q concurrent plane streams do not all map to the same HBM channel
+  lay->plane = (int64_t)align_up((uint64_t)p->ny * lay->pitch, 256) + 256;
+  const int64_t ncells = (int64_t)p->nx * p->ny;
+  lay->ntiles = (int32_t)((ncells + lay->cells_per_tile - 1) / lay->cells_per_tile);
+  lay->hist_cap = p->history_capacity ? p->history_capacity : p->max_steps;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o;
+    o = align_up(o + std::max<uint64_t>(bytes, 1), kAlign);
+    return at;
+  };
+  lay->off_desc = take(sizeof(SolveDesc));
+  lay->off_state = take(sizeof(SolveState));
+  lay->off_work = take(sizeof(WorkItem) * lay->ntiles);
+  lay->off_solves = take(sizeof(int32_t));
+  lay->off_slot = take(sizeof(int32_t) * lay->ntiles);
+  lay->off_part = 0;  // set after plan_links (needs nslots); reserve the worst case
+  lay->off_part = take(sizeof(double) * 2 * (uint64_t)lay->ntiles);
+  lay->off_drive = take(sizeof(Drive) * (uint64_t)p->max_steps);
+  lay->off_hist = take(sizeof(double) * 2 * (uint64_t)lay->hist_cap);
+  lay->buf_bytes = (uint64_t)L.Q * lay->plane * es;
+  o = align_up(o, 4096);
+  lay->off_buf[0] = take(lay->buf_bytes);
+  o = align_up(o, 4096);
+  lay->off_buf[1] = take(lay->buf_bytes);
+  lay->total = o;
+}
+
+
+}  // namespace
+
+namespace {
+
+int init_solver(lbm_solver* s) {
+  const lbm_params* p = &s->p;
+  const Layout& lay = s->lay;
+  char* b = s->base;
+  std::vector<int32_t> slot;
+  double fstatic[2];
+  int32_t nslots = 0;
+  plan_links(p, s->lat, lay, &slot, &nslots, fstatic);
+  s->lay.nslots = nslots;
+
+  SolveDesc& d = s->desc;
+  std::memset(&d, 0, sizeof(d));
+  d.buf[0] = b + lay.off_buf[0];
+  d.buf[1] = b + lay.off_buf[1];
+  d.drive = reinterpret_cast<const Drive*>(b + lay.off_drive);
+  d.hist = reinterpret_cast<double*>(b + lay.off_hist);
+  d.state = reinterpret_cast<SolveState*>(b + lay.off_state);
+  d.partials = reinterpret_cast<double*>(b + lay.off_part);
+  d.slot = reinterpret_cast<const int32_t*>(b + lay.off_slot);
+  d.plane = lay.plane;
+  d.max_steps = p->max_steps;
+  d.hist_cap = lay.hist_cap;
+  d.lockin_first = p->lockin_first;
+  d.lockin_count = p->lockin_count;
+  d.nx = p->nx;
+  d.ny = p->ny;
+  d.pitch = (int32_t)lay.pitch;
+  d.ncells = p->nx * p->ny;
+  d.geom = (int32_t)p->geometry;
+  d.far = (int32_t)p->far;
+  if (p->geometry == LBM_GEOM_BOX) {
+    d.bx0 = p->box_x0;
+    d.by0 = p->box_y0;
+    d.bx1 = p->box_x0 + p->box_lx;
+    d.by1 = p->box_y0 + p->box_ly;
+  }
+  d.ntiles = lay.ntiles;
+  d.nslots = nslots;
+  d.cells_per_tile = lay.cells_per_tile;
+  d.inv_tau = std::isinf(p->tau) ? 0.0 : 1.0 / p->tau;
+  d.rho0 = p->rho0;
+  d.ladd_scale = 2.0 * p->rho0 / s->lat.lw.theta;
+  d.fstatic[0] = fstatic[0];
+  d.fstatic[1] = fstatic[1];
+
+  for (int k = 0; k < 8; ++k) s->klat.w[k] = s->lat.lw.w_orbit[k];
+  s->klat.theta = s->lat.lw.theta;
+
+  std::vector<WorkItem> work(lay.ntiles);
+  for (int t = 0; t < lay.ntiles; ++t) work[t] = WorkItem{0, t};
+  std::vector<Drive> drive((size_t)p->max_steps);
+  for (int64_t n = 0; n < p->max_steps; ++n) {
+    const double arg = p->omega * ((double)n + 0.5);
+    drive[n].u = p->u0 * std::sin(arg);
+    drive[n].s = std::sin(arg);
+    drive[n].c = std::cos(arg);
+  }
+  const int32_t solve0 = 0;
+  s->d_desc = reinterpret_cast<SolveDesc*>(b + lay.off_desc);
+  s->d_work = reinterpret_cast<WorkItem*>(b + lay.off_work);
+  s->d_solves = reinterpret_cast<int32_t*>(b + lay.off_solves);
+
+  hipStream_t st = s->stream;
+  int rc;
+  if ((rc = hip_rc(hipMemcpyAsync(s->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, st)))) return rc;
+  if ((rc = hip_rc(hipMemcpyAsync(s->d_work, work.data(), sizeof(WorkItem) * work.size(),
+                                  hipMemcpyHostToDevice, st))))
+    return rc;
+  if ((rc = hip_rc(hipMemcpyAsync(s->d_solves, &solve0, sizeof(solve0), hipMemcpyHostToDevice,
+                                  st))))
+    return rc;
+  if ((rc = hip_rc(hipMemcpyAsync(b + lay.off_slot, slot.data(), sizeof(int32_t) * slot.size(),
+                                  hipMemcpyHostToDevice, st))))
+    return rc;
+  if ((rc = hip_rc(hipMemcpyAsync(b + lay.off_drive, drive.data(), sizeof(Drive) * drive.size(),
+                                  hipMemcpyHostToDevice, st))))
+    return rc;
+  // rest state (zero deviations), zero counters, sums and history
+  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_state, 0, sizeof(SolveState), st)))) return rc;
+  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_part, 0, sizeof(double) * 2 * lay.ntiles, st))))
+    return rc;
+  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_hist, 0, sizeof(double) * 2 * lay.hist_cap, st))))
+    return rc;
+  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_buf[0], 0, lay.buf_bytes, st)))) return rc;
+  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_buf[1], 0, lay.buf_bytes, st)))) return rc;
+  return hip_rc(hipStreamSynchronize(st));
+}
+
+int create_common(const lbm_params* p, void* stream, void* dev_buf, uint64_t bytes,
+                  lbm_solver** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  lbm_solver* s = new (std::nothrow) lbm_solver();
+  if (!s) return LBM_ENOMEM;
+  int rc = validate(p, &s->lat);
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  s->p = *p;
+  make_layout(p, s->lat, &s->lay);
+  s->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return LBM_EHIP;
+  }
+  if (dev_buf) {
+    if (bytes < s->lay.total || (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) != 0) {
+      delete s;
+      return bytes < s->lay.total ? LBM_ENOMEM : LBM_EINVAL;
+    }
+    s->base = static_cast<char*>(dev_buf);
+  } else {
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, s->lay.total) != hipSuccess) {
+      (void)hipGetLastError();
+      delete s;
+      return LBM_ENOMEM;
+    }
+    s->base = static_cast<char*>(ptr);
+    s->owned = true;
+  }
+  rc = init_solver(s);
+  if (rc) {
+    if (s->owned) (void)hipFree(s->base);
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return LBM_OK;
+}
+
+int sync_and_check(lbm_solver* s) {
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
+  if (!s->sticky_unstable) {
+    int32_t flag = 0;
+    if (hipMemcpy(&flag, &s->desc.state->unstable, sizeof(flag), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return LBM_EHIP;
+    s->sticky_unstable = flag != 0;
+  }
+  return s->sticky_unstable ? LBM_EUNSTABLE : LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_params_init(lbm_params* p) {
+  if (!p) return LBM_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->abi_version = LBM_ABI_VERSION;
+  p->lattice = LBM_D2Q37;
+  p->storage = LBM_STORE_F32_DEV;
+  p->collision = LBM_COLL_REGULARIZED;
+  p->wall = LBM_WALL_BB;
+  p->geometry = LBM_GEOM_PLATE;
+  p->far = LBM_FAR_WALL;
+  p->rho0 = 1.0;
+  return LBM_OK;
+}
+
+int lbm_lattice(int Q, int32_t* vx, int32_t* vy, double* w, double* theta) {
+  HostLattice h;
+  if (!host_lattice(Q, &h)) return LBM_EINVAL;
+  for (int i = 0; i < Q; ++i) {
+    if (vx) vx[i] = h.vx[i];
+    if (vy) vy[i] = h.vy[i];
+    if (w) w[i] = h.lw.w_orbit[h.orbit[i]];
+  }
+  if (theta) *theta = h.lw.theta;
+  return LBM_OK;
+}
+
+int lbm_required_bytes(const lbm_params* p, uint64_t* bytes) {
+  if (!bytes) return LBM_EINVAL;
+  HostLattice lat;
+  int rc = validate(p, &lat);
+  if (rc) return rc;
+  Layout lay;
+  make_layout(p, lat, &lay);
+  *bytes = lay.total;
+  return LBM_OK;
+}
+
+int lbm_create(const lbm_params* p, void* hip_stream, lbm_solver** out) {
+  return create_common(p, hip_stream, nullptr, 0, out);
+}
+
+int lbm_create_in(const lbm_params* p, void* hip_stream, void* dev_buf, uint64_t bytes,
+                  lbm_solver** out) {
+  if (!dev_buf) return LBM_EINVAL;
+  return create_common(p, hip_stream, dev_buf, bytes, out);
+}
+
+int lbm_step(lbm_solver* s, int64_t nsteps) {
+  if (!s || nsteps < 0) return LBM_EINVAL;
+  if (s->steps + nsteps > s->p.max_steps) return LBM_ERANGE;
+  const bool f64 = s->p.storage == LBM_STORE_F64;
+  const bool bgk = s->p.collision == LBM_COLL_BGK;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (launch_step((int)s->p.lattice, f64, bgk, s->d_desc, s->d_work, s->lay.ntiles, s->klat,
+                    s->stream) != hipSuccess)
+      return LBM_EHIP;
+    if (launch_finalize(s->d_desc, s->d_solves, 1, s->stream) != hipSuccess) return LBM_EHIP;
+    ++s->steps;
+  }
+  return LBM_OK;
+}
+
+int lbm_synchronize(lbm_solver* s) {
+  if (!s) return LBM_EINVAL;
+  return sync_and_check(s);
+}
+
+int lbm_steps_done(const lbm_solver* s, int64_t* n) {
+  if (!s || !n) return LBM_EINVAL;
+  *n = s->steps;
+  return LBM_OK;
+}
+
+int lbm_force_history(lbm_solver* s, int64_t first, int64_t count, double* fx, double* fy) {
+  if (!s || first < 0 || count < 0) return LBM_EINVAL;
+  const int64_t cap = s->lay.hist_cap;
+  if (first + count > s->steps || first < std::max(s->hist_from, s->steps - std::min(s->steps, cap)))
+    return LBM_ERANGE;
+  int rc = sync_and_check(s);
+  if (rc && rc != LBM_EUNSTABLE) return rc;
+  std::vector<double> tmp((size_t)count * 2);
+  int64_t done = 0;
+  while (done < count) {
+    const int64_t h = (first + done) % cap;
+    const int64_t run = std::min(count - done, cap - h);
+    if (hipMemcpy(tmp.data() + 2 * done, s->desc.hist + 2 * h, sizeof(double) * 2 * run,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return LBM_EHIP;
+    done += run;
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    if (fx) fx[i] = tmp[2 * i];
+    if (fy) fy[i] = tmp[2 * i + 1];
+  }
+  return rc;
+}
+
+int lbm_lockin(lbm_solver* s, double sums[6], int64_t* nsamples) {
+  if (!s || !sums) return LBM_EINVAL;
+  int rc = sync_and_check(s);
+  if (rc && rc != LBM_EUNSTABLE) return rc;
+  SolveState st;
+  if (hipMemcpy(&st, s->desc.state, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return LBM_EHIP;
+  for (int k = 0; k < 6; ++k) sums[k] = st.lockin[k];
+  if (nsamples)
+    *nsamples = std::max<int64_t>(
+        0, std::min(s->steps, s->p.lockin_first + s->p.lockin_count) - s->p.lockin_first);
+  return rc;
+}
+
+int lbm_impedance(lbm_solver* s, double out[5]) {
+  if (!s || !out) return LBM_EINVAL;
+  double sums[6];
+  int64_t ns = 0;
+  int rc = lbm_lockin(s, sums, &ns);
+  if (rc && rc != LBM_EUNSTABLE) return rc;
+  if (ns < 3) return LBM_ERANGE;
+  // normal equations of F ~ a sin + b cos + c with the drive table's basis
+  long double G[3][4] = {{0}};
+  for (int64_t n = s->p.lockin_first; n < s->p.lockin_first + ns; ++n) {
+    const double arg = s->p.omega * ((double)n + 0.5);
+    const long double b[3] = {std::sin(arg), std::cos(arg), 1.0L};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) G[r][c] += b[r] * b[c];
+  }
+  G[0][3] = sums[0];
+  G[1][3] = sums[1];
+  G[2][3] = sums[2];
+  for (int c = 0; c < 3; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 3; ++r)
+      if (std::fabs(G[r][c]) > std::fabs(G[piv][c])) piv = r;
+    if (G[piv][c] == 0) return LBM_ERANGE;
+    for (int k = 0; k < 4; ++k) std::swap(G[c][k], G[piv][k]);
+    for (int r = 0; r < 3; ++r) {
+      if (r == c) continue;
+      const long double m = G[r][c] / G[c][c];
+      for (int k = c; k < 4; ++k) G[r][k] -= m * G[c][k];
+    }
+  }
+  const long double a = G[0][3] / G[0][0], b = G[1][3] / G[1][1], c = G[2][3] / G[2][2];
+  out[0] = (double)a;
+  out[1] = (double)b;
+  out[2] = (double)c;
+  out[3] = (double)(-a / s->p.u0);
+  out[4] = (double)(-b / s->p.u0);
+  return rc;
+}
+
+namespace {
+
+// Copy the current buffer out as FP64 [q][y][x]; with_rest adds w_i rho0.
+int copy_out(lbm_solver* s, double* host, uint64_t n, bool with_rest) {
+  if (!s || !host) return LBM_EINVAL;
+  const lbm_params& p = s->p;
+  const int Q = s->lat.Q;
+  if (n != (uint64_t)Q * p.ny * p.nx) return LBM_EINVAL;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
+  const bool f64 = p.storage == LBM_STORE_F64;
+  std::vector<char> stage(s->lay.buf_bytes);
+  if (hipMemcpy(stage.data(), s->desc.buf[s->steps & 1], s->lay.buf_bytes,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return LBM_EHIP;
+  for (int q = 0; q < Q; ++q) {
+    const double wr = with_rest ? s->lat.lw.w_orbit[s->lat.orbit[q]] * p.rho0 : 0.0;
+    for (int y = 0; y < p.ny; ++y)
+      for (int x = 0; x < p.nx; ++x) {
+        const int64_t src = q * s->lay.plane + (int64_t)y * s->lay.pitch + x;
+        const double dv = f64 ? reinterpret_cast<const double*>(stage.data())[src]
+                              : (double)reinterpret_cast<const float*>(stage.data())[src];
+        host[((size_t)q * p.ny + y) * p.nx + x] = in_body(&p, x, y) ? 0.0 : wr + dv;
+      }
+  }
+  return LBM_OK;
+}
+
+// Copy FP64 [q][y][x] into the current buffer; with_rest subtracts w_i rho0.
+int copy_in(lbm_solver* s, const double* host, uint64_t n, bool with_rest) {
+  if (!s || !host) return LBM_EINVAL;
+  const lbm_params& p = s->p;
+  const int Q = s->lat.Q;
+  if (n != (uint64_t)Q * p.ny * p.nx) return LBM_EINVAL;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
+  const bool f64 = p.storage == LBM_STORE_F64;
+  std::vector<char> stage(s->lay.buf_bytes, 0);
+  for (int q = 0; q < Q; ++q) {
+    const double wr = with_rest ? s->lat.lw.w_orbit[s->lat.orbit[q]] * p.rho0 : 0.0;
+    for (int y = 0; y < p.ny; ++y)
+      for (int x = 0; x < p.nx; ++x) {
+        const int64_t dst = q * s->lay.plane + (int64_t)y * s->lay.pitch + x;
+        const double dv = in_body(&p, x, y) ? 0.0 : host[((size_t)q * p.ny + y) * p.nx + x] - wr;
+        if (f64) reinterpret_cast<double*>(stage.data())[dst] = dv;
+        else reinterpret_cast<float*>(stage.data())[dst] = (float)dv;
+      }
+  }
+  if (hipMemcpy(s->desc.buf[s->steps & 1], stage.data(), s->lay.buf_bytes,
+                hipMemcpyHostToDevice) != hipSuccess)
+    return LBM_EHIP;
+  return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_get_populations(lbm_solver* s, double* host, uint64_t n) {
+  return copy_out(s, host, n, true);
+}
+
+int lbm_set_populations(lbm_solver* s, const double* host, uint64_t n) {
+  return copy_in(s, host, n, true);
+}
+
+int lbm_get_deviations(lbm_solver* s, double* host, uint64_t n) {
+  return copy_out(s, host, n, false);
+}
+
+int lbm_set_deviations(lbm_solver* s, const double* host, uint64_t n) {
+  return copy_in(s, host, n, false);
+}
+
+int lbm_seek(lbm_solver* s, int64_t step, const double lockin_sums[6]) {
+  if (!s || step < 0 || step >= s->p.max_steps) return LBM_EINVAL;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
+  if ((step & 1) != (s->steps & 1) &&
+      hipMemcpy(s->desc.buf[step & 1], s->desc.buf[s->steps & 1], s->lay.buf_bytes,
+                hipMemcpyDeviceToDevice) != hipSuccess)
+    return LBM_EHIP;
+  SolveState st{};
+  st.step = step;
+  for (int k = 0; k < 6; ++k) st.lockin[k] = lockin_sums ? lockin_sums[k] : 0.0;
+  if (hipMemcpy(s->desc.state, &st, sizeof(st), hipMemcpyHostToDevice) != hipSuccess)
+    return LBM_EHIP;
+  s->steps = step;
+  s->hist_from = step;
+  s->sticky_unstable = false;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_solver* s) {
+  if (!s) return LBM_OK;
+  int rc = hipStreamSynchronize(s->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+  if (s->owned && hipFree(s->base) != hipSuccess) rc = LBM_EHIP;
+  delete s;
+  return rc;
+}
+
+const char* lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory or buffer too small";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ERANGE: return "out of range";
+    case LBM_EUNSTABLE: return "unstable: non-positive or non-finite density";
+    case LBM_EABI: return "ABI version mismatch";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,301 @@
+// Batched execution: many solvers (uneven lattices, same velocity set,
+// storage and collision) advanced by one fused stream-collide launch per
+// step over the tiles of every member, plus one finalize launch that reduces
+// each member's wall force.  Members join and leave between steps
+// (continuous batching); a member stops when it reaches its max_steps.
+// Steady-state chunks are replayed from a captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace lbm;
+
+struct lbm_batch {
+  hipStream_t stream = nullptr;
+  std::vector<lbm_solver*> members;
+  int Q = 0;
+  uint32_t storage = 0, collision = 0;
+  // current launch set (members that still have steps to run)
+  std::vector<lbm_solver*> active;
+  bool dirty = true;
+  int nwork = 0;
+  SolveDesc* d_descs = nullptr;
+  WorkItem* d_work = nullptr;
+  int32_t* d_solves = nullptr;
+  size_t cap_descs = 0, cap_work = 0, cap_solves = 0;
+  // graph of `graph_steps` steps for the current launch set
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0;
+  int graph_chunk = 32;
+  bool graphs_enabled = true;
+  // per-launch timing of the fused step kernel
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double kernel_ms = 0;
+  int64_t launches = 0;
+};
+
+namespace {
+
+void drop_graph(lbm_batch* b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_steps = 0;
+}
+
+template <class T>
+int grow(T** ptr, size_t* cap, size_t need) {
+  if (need <= *cap) return LBM_OK;
+  size_t n = std::max(need, *cap * 2);
+  if (*ptr) (void)hipFree(*ptr);
+  *ptr = nullptr;
+  *cap = 0;
+  if (hipMalloc(reinterpret_cast<void**>(ptr), n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return LBM_ENOMEM;
+  }
+  *cap = n;
+  return LBM_OK;
+}
+
+// Rebuild the device launch set from the members that have steps left.
+int refresh(lbm_batch* b) {
+  std::vector<lbm_solver*> act;
+  for (lbm_solver* s : b->members)
+    if (s->steps < s->p.max_steps) act.push_back(s);
+  if (!b->dirty && act == b->active) return LBM_OK;
+  drop_graph(b);
+  b->active = act;
+  b->dirty = false;
+  std::vector<SolveDesc> descs;
+  std::vector<WorkItem> work;
+  std::vector<int32_t> solves;
+  for (size_t i = 0; i < act.size(); ++i) {
+    descs.push_back(act[i]->desc);
+    solves.push_back((int32_t)i);
+    for (int t = 0; t < act[i]->lay.ntiles; ++t) work.push_back(WorkItem{(int32_t)i, t});
+  }
+  b->nwork = (int)work.size();
+  if (act.empty()) return LBM_OK;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EHIP;
+  int rc;
+  if ((rc = grow(&b->d_descs, &b->cap_descs, descs.size()))) return rc;
+  if ((rc = grow(&b->d_work, &b->cap_work, work.size()))) return rc;
+  if ((rc = grow(&b->d_solves, &b->cap_solves, solves.size()))) return rc;
+  if (hipMemcpy(b->d_descs, descs.data(), sizeof(SolveDesc) * descs.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_work, work.data(), sizeof(WorkItem) * work.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_solves, solves.data(), sizeof(int32_t) * solves.size(),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return LBM_EHIP;
+  return LBM_OK;
+}
+
+hipEvent_t next_event(lbm_batch* b) {
+  if (b->ev_used == b->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    b->ev_pool.push_back(e);
+  }
+  return b->ev_pool[b->ev_used++];
+}
+
+// Sum the durations of the recorded step-kernel launches (waits).
+int collect_timing(lbm_batch* b) {
+  if (b->ev_used == 0) return LBM_OK;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EHIP;
+  for (size_t i = 0; i + 1 < b->ev_used; i += 2) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, b->ev_pool[i], b->ev_pool[i + 1]) != hipSuccess) return LBM_EHIP;
+    b->kernel_ms += ms;
+    ++b->launches;
+  }
+  b->ev_used = 0;
+  return LBM_OK;
+}
+
+int launch_one(lbm_batch* b) {
+  const bool f64 = b->storage == LBM_STORE_F64, bgk = b->collision == LBM_COLL_BGK;
+  const KernelLattice& lat = b->active[0]->klat;
+  if (b->timing) {
+    if (b->ev_used + 2 > 4096) {
+      int rc = collect_timing(b);
+      if (rc) return rc;
+    }
+    hipEvent_t e0 = next_event(b), e1 = next_event(b);
+    if (!e0 || !e1) return LBM_EHIP;
+    if (hipEventRecord(e0, b->stream) != hipSuccess) return LBM_EHIP;
+    if (launch_step(b->Q, f64, bgk, b->d_descs, b->d_work, b->nwork, lat, b->stream) != hipSuccess)
+      return LBM_EHIP;
+    if (hipEventRecord(e1, b->stream) != hipSuccess) return LBM_EHIP;
+  } else if (launch_step(b->Q, f64, bgk, b->d_descs, b->d_work, b->nwork, lat, b->stream) !=
+             hipSuccess) {
+    return LBM_EHIP;
+  }
+  if (launch_finalize(b->d_descs, b->d_solves, (int)b->active.size(), b->stream) != hipSuccess)
+    return LBM_EHIP;
+  return LBM_OK;
+}
+
+// Capture graph_chunk steps of the current launch set into a graph.
+bool capture(lbm_batch* b) {
+  if (b->stream == nullptr) return false;  // the null stream cannot be captured
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  bool ok = true;
+  const bool timing = b->timing;
+  b->timing = false;
+  for (int k = 0; k < b->graph_chunk && ok; ++k) ok = launch_one(b) == LBM_OK;
+  b->timing = timing;
+  if (hipStreamEndCapture(b->stream, &g) != hipSuccess || !ok) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    return false;
+  }
+  hipGraphExec_t ex = nullptr;
+  const bool inst = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipGraphDestroy(g);
+  if (!inst) {
+    (void)hipGetLastError();
+    return false;
+  }
+  b->graph = ex;
+  b->graph_steps = b->graph_chunk;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(void* hip_stream, lbm_batch** out) {
+  if (!out) return LBM_EINVAL;
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_ENOMEM;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_add(lbm_batch* b, lbm_solver* s) {
+  if (!b || !s) return LBM_EINVAL;
+  if (s->stream != b->stream) return LBM_EINVAL;
+  if (std::find(b->members.begin(), b->members.end(), s) != b->members.end()) return LBM_EINVAL;
+  if (b->members.empty()) {
+    b->Q = (int)s->p.lattice;
+    b->storage = s->p.storage;
+    b->collision = s->p.collision;
+  } else if ((int)s->p.lattice != b->Q || s->p.storage != b->storage ||
+             s->p.collision != b->collision) {
+    return LBM_EINVAL;
+  }
+  b->members.push_back(s);
+  b->dirty = true;
+  return LBM_OK;
+}
+
+int lbm_batch_remove(lbm_batch* b, lbm_solver* s) {
+  if (!b || !s) return LBM_EINVAL;
+  auto it = std::find(b->members.begin(), b->members.end(), s);
+  if (it == b->members.end()) return LBM_EINVAL;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EHIP;
+  b->members.erase(it);
+  b->dirty = true;
+  if (b->members.empty()) {
+    b->Q = 0;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_size(const lbm_batch* b, int* members, int* active) {
+  if (!b) return LBM_EINVAL;
+  if (members) *members = (int)b->members.size();
+  if (active) {
+    int n = 0;
+    for (lbm_solver* s : b->members) n += s->steps < s->p.max_steps;
+    *active = n;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return LBM_EINVAL;
+  int64_t left = nsteps;
+  while (left > 0) {
+    int rc = refresh(b);
+    if (rc) return rc;
+    if (b->active.empty()) break;
+    int64_t chunk = left;
+    for (lbm_solver* s : b->active) chunk = std::min(chunk, s->p.max_steps - s->steps);
+    int64_t k = 0;
+    if (b->graphs_enabled && !b->timing && chunk >= b->graph_chunk) {
+      if (!b->graph && !capture(b)) b->graphs_enabled = false;
+      for (; b->graph && k + b->graph_steps <= chunk; k += b->graph_steps)
+        if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return LBM_EHIP;
+    }
+    for (; k < chunk; ++k)
+      if ((rc = launch_one(b))) return rc;
+    for (lbm_solver* s : b->active) s->steps += chunk;
+    left -= chunk;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_synchronize(lbm_batch* b) {
+  if (!b) return LBM_EINVAL;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EHIP;
+  int worst = LBM_OK;
+  for (lbm_solver* s : b->members) {
+    int rc = lbm_synchronize(s);
+    if (rc && !worst) worst = rc;
+  }
+  return worst;
+}
+
+int lbm_batch_set_graphs(lbm_batch* b, int steps_per_graph) {
+  if (!b || steps_per_graph < 0) return LBM_EINVAL;
+  drop_graph(b);
+  b->graphs_enabled = steps_per_graph > 0;
+  if (steps_per_graph > 0) b->graph_chunk = steps_per_graph;
+  return LBM_OK;
+}
+
+int lbm_batch_timing(lbm_batch* b, int enable) {
+  if (!b) return LBM_EINVAL;
+  int rc = collect_timing(b);
+  b->timing = enable != 0;
+  b->kernel_ms = 0;
+  b->launches = 0;
+  return rc;
+}
+
+int lbm_batch_kernel_time(lbm_batch* b, double* ms, int64_t* launches) {
+  if (!b) return LBM_EINVAL;
+  int rc = collect_timing(b);
+  if (ms) *ms = b->kernel_ms;
+  if (launches) *launches = b->launches;
+  return rc;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_OK;
+  int rc = hipStreamSynchronize(b->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+  drop_graph(b);
+  for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+  if (b->d_descs) (void)hipFree(b->d_descs);
+  if (b->d_work) (void)hipFree(b->d_work);
+  if (b->d_solves) (void)hipFree(b->d_solves);
+  delete b;
+  return rc;
+}
+
+}  // extern "C"

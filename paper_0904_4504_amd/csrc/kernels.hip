@@ -1,0 +1,332 @@
+// Lattice-BGK hot path for gfx950: fused pull-stream + regularized collision
+// with moving-wall bounce-back and FP64 momentum-exchange force, and the
+// per-step force finalisation with lock-in accumulation.
+//
+// Method (Sec. 5): advection f_i^adv(x) = f_i(x - v_i) (eq. advection);
+// moments rho, rho u, Pi of f^adv (eq. MME_lbgk); H2 equilibrium (eq.
+// feq_h2); regularized non-equilibrium part (eq. fne) relaxed by (1 - 1/tau)
+// (eq. regularization).  Bounce-back (Sec. 4, eq. BB) in its linearised
+// half-way lattice form with the moving-wall term 2 w_i rho0 (v_i.U_w)/theta;
+// wall drive U_w = U0 sin(omega t) along x (Sec. 6).  The force on the body is
+// the momentum exchanged by the bounced populations; its dissipative and
+// inertial parts (Sec. 2, F_f = -m(gamma x_t + beta x_tt)) come from the
+// lock-in sums.
+//
+// Storage: deviations delta f_i = f_i - w_i rho0 in FP64 or FP32, structure
+// of arrays, plane q at buf + q*plane, cell (x, y) at y*pitch + x.  Written in
+// deviation form the regularized collision needs only six sums of the pulled
+// populations (delta rho, j, P = sum delta f v v); its output is
+//   delta f_i^post = w_i [ a0 + v_i . b + c_xx vx^2 + c_xy vx vy + c_yy vy^2 ]
+// with B = A' - omega_r (A' - j j / rho), A' = P - delta rho theta I,
+//   a0 = delta rho - tr(B)/(2 theta), b = j/theta, c_xx = B_xx/(2 theta^2),
+//   c_xy = B_xy/theta^2, c_yy = B_yy/(2 theta^2),
+// which equals f^eq + (1 - 1/tau) fne of the paper minus w_i rho0 (the H2
+// equilibrium and the projected non-equilibrium part expand in the same
+// Hermite basis).  omega_r = 1/tau is kept separate from 1 - 1/tau so that
+// large tau loses no precision in FP32.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "lattice.hpp"
+#include "solver.hpp"
+
+namespace lbm {
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap so that consecutive tiles -- which share the misaligned edge
+// cache lines of the shifted pulls -- run on the same XCD.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int x = b & 7, l = b >> 3;
+  const int q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + l;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Pull of population q into fluid cell (x, y) when the cell lies within R
+// cells of the domain edge or of the body: periodic wrap, bounce-back at the
+// moving wall / body (with its force contribution), stationary far wall or
+// rest-equilibrium far field (delta f = 0).
+template <class L, typename S, int q>
+__device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__ fin, int x,
+                                       int y, double ladd, double wq, double& fx, double& fy) {
+  constexpr int vx = L::vx[q], vy = L::vy[q];
+  constexpr int o = opposite<L>(q);
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+  const int64_t plane = d.plane;
+  int sx = x - vx, sy = y - vy;
+  if (d.geom == GEOM_PERIODIC) {
+    sx += sx < 0 ? nx : 0;
+    sx -= sx >= nx ? nx : 0;
+    sy += sy < 0 ? ny : 0;
+    sy -= sy >= ny ? ny : 0;
+    return fin[q * plane + (int64_t)sy * pitch + sx];
+  }
+  if (d.geom == GEOM_PLATE) {
+    sx += sx < 0 ? nx : 0;
+    sx -= sx >= nx ? nx : 0;
+    if constexpr (vy > 0) {
+      if (sy < 0) {
+        // crossed the moving wall at y = -1/2: retrace in y, keep x
+        const int py = -1 - sy;
+        const S fr = fin[o * plane + (int64_t)py * pitch + x];
+        const double lad = wq * vx * ladd;
+        const double m = 2.0 * (double)fr + lad;
+        fx -= vx * m;
+        fy -= vy * m;
+        return fr + (S)lad;
+      }
+    }
+    if constexpr (vy < 0) {
+      if (sy >= ny) {
+        if (d.far == FAR_EQ) return S(0);
+        const int py = 2 * ny - 1 - sy;  // stationary wall at y = ny - 1/2
+        return fin[o * plane + (int64_t)py * pitch + x];
+      }
+    }
+    return fin[q * plane + (int64_t)sy * pitch + sx];
+  }
+  // box in a rest-equilibrium far field
+  if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) return S(0);
+  if (sx >= d.bx0 && sx < d.bx1 && sy >= d.by0 && sy < d.by1) {
+    // per axis: mirror the source through the face plane when the arrival
+    // lies outside the body's range on that axis, else keep the arrival
+    int px = x, py = y;
+    if (x < d.bx0) px = 2 * d.bx0 - 1 - sx;
+    else if (x >= d.bx1) px = 2 * d.bx1 - 1 - sx;
+    if (y < d.by0) py = 2 * d.by0 - 1 - sy;
+    else if (y >= d.by1) py = 2 * d.by1 - 1 - sy;
+    const S fr = fin[o * plane + (int64_t)py * pitch + px];
+    const double lad = wq * vx * ladd;
+    const double m = 2.0 * (double)fr + lad;
+    fx -= vx * m;
+    fy -= vy * m;
+    return fr + (S)lad;
+  }
+  return fin[q * plane + (int64_t)sy * pitch + sx];
+}
+
+template <class L, typename S, bool BGK>
+__global__ __launch_bounds__(kBlock) void step_kernel(const SolveDesc* __restrict__ descs,
+                                                      const WorkItem* __restrict__ work,
+                                                      KernelLattice lat) {
+  constexpr int Q = L::Q, R = L::R;
+  const WorkItem wi = work[xcd_remap(blockIdx.x, gridDim.x)];
+  const SolveDesc& d = descs[wi.solve];
+  const int64_t n = d.state->step;
+  const S* __restrict__ fin = static_cast<const S*>(d.buf[n & 1]);
+  S* __restrict__ fout = static_cast<S*>(d.buf[(n & 1) ^ 1]);
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+  const int64_t plane = d.plane;
+
+  const int c = wi.tile * d.cells_per_tile + (int)threadIdx.x;
+  const bool active = c < d.ncells;
+  const int y = active ? c / nx : 0;
+  const int x = active ? c - y * nx : 0;
+  const bool is_box = d.geom == GEOM_BOX;
+  const bool solid = is_box && x >= d.bx0 && x < d.bx1 && y >= d.by0 && y < d.by1;
+  bool interior = x >= R && x < nx - R && y >= R && y < ny - R;
+  if (is_box) interior = interior && !(x >= d.bx0 - R && x < d.bx1 + R && y >= d.by0 - R &&
+                                       y < d.by1 + R);
+  const bool fluid = active && !solid;
+  const int64_t idx = (int64_t)y * pitch + x;
+
+  S f[Q];
+  double fx = 0.0, fy = 0.0;
+  if (fluid && interior) {
+    static_for<0, Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int off = 0;  // keeps the offset expression below in int64
+      f[q] = fin[q * plane + idx - ((int64_t)L::vy[q] * pitch + L::vx[q]) + off];
+    });
+  } else if (fluid) {
+    const double ladd = d.ladd_scale * d.drive[n].u;
+    static_for<0, Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      f[q] = pull_edge<L, S, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], fx, fy);
+    });
+  } else {
+    static_for<0, Q>([&](auto qc) { f[decltype(qc)::value] = S(0); });
+  }
+
+  // moments of the pulled deviations
+  S drho = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
+  static_for<0, Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int vx = L::vx[q], vy = L::vy[q];
+    const S v = f[q];
+    drho += v;
+    if constexpr (vx != 0) jx += S(vx) * v;
+    if constexpr (vy != 0) jy += S(vy) * v;
+    if constexpr (vx != 0) pxx += S(vx * vx) * v;
+    if constexpr (vx * vy != 0) pxy += S(vx * vy) * v;
+    if constexpr (vy != 0) pyy += S(vy * vy) * v;
+  });
+
+  const S th = (S)lat.theta;
+  const S inv_th = (S)(1.0 / lat.theta);
+  const S h2 = (S)(0.5 / (lat.theta * lat.theta));
+  const S om = (S)d.inv_tau;
+  const S rho = (S)d.rho0 + drho;
+  const S inv_rho = S(1) / rho;
+  const S uxx = jx * jx * inv_rho, uxy = jx * jy * inv_rho, uyy = jy * jy * inv_rho;
+
+  if (fluid && !(rho > S(0) && rho < S(INFINITY))) d.state->unstable = 1;
+
+  if constexpr (!BGK) {
+    const S axx = pxx - drho * th, ayy = pyy - drho * th, axy = pxy;
+    const S bxx = axx - om * (axx - uxx);
+    const S bxy = axy - om * (axy - uxy);
+    const S byy = ayy - om * (ayy - uyy);
+    const S a0 = drho - (bxx + byy) * (S(0.5) * inv_th);
+    const S bx = jx * inv_th, by = jy * inv_th;
+    const S cxx = bxx * h2, cxy = bxy * (S(2) * h2), cyy = byy * h2;
+    if (fluid) {
+      static_for<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int vx = L::vx[q], vy = L::vy[q];
+        S p = a0;
+        if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
+        if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
+        if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
+        fout[q * plane + idx] = (S)lat.w[L::orbit[q]] * p;
+      });
+    }
+  } else {
+    // plain BGK: delta f^post = delta f + omega_r (delta f^eq - delta f)
+    const S a0 = drho - (uxx + uyy) * (S(0.5) * inv_th);
+    const S bx = jx * inv_th, by = jy * inv_th;
+    const S cxx = uxx * h2, cxy = uxy * (S(2) * h2), cyy = uyy * h2;
+    if (fluid) {
+      static_for<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int vx = L::vx[q], vy = L::vy[q];
+        S p = a0;
+        if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
+        if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
+        if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
+        const S feq = (S)lat.w[L::orbit[q]] * p;
+        fout[q * plane + idx] = f[q] + om * (feq - f[q]);
+      });
+    }
+  }
+
+  // per-tile force partial (fixed reduction order: lanes, then waves)
+  const int slot = d.slot[wi.tile];
+  if (slot >= 0) {
+    __shared__ double red[2][kBlock / 64];
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      red[0][wave] = fx;
+      red[1][wave] = fy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int k = 0; k < kBlock / 64; ++k) {
+        sx += red[0][k];
+        sy += red[1][k];
+      }
+      d.partials[2 * slot] = sx;
+      d.partials[2 * slot + 1] = sy;
+    }
+  }
+}
+
+// One workgroup per solve: sum the tile partials in slot order, add the
+// rest-state constant, append F_n to the history ring, accumulate the lock-in
+// sums when n lies in the window, and advance the step counter.
+__global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __restrict__ descs,
+                                                          const int32_t* __restrict__ solves) {
+  const SolveDesc& d = descs[solves[blockIdx.x]];
+  double fx = 0.0, fy = 0.0;
+  for (int s = threadIdx.x; s < d.nslots; s += kBlock) {
+    fx += d.partials[2 * s];
+    fy += d.partials[2 * s + 1];
+  }
+  __shared__ double red[2][kBlock / 64];
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wave] = fx;
+    red[1][wave] = fy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    fx = d.fstatic[0];
+    fy = d.fstatic[1];
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) {
+      sx += red[0][k];
+      sy += red[1][k];
+    }
+    fx += sx;
+    fy += sy;
+    SolveState* st = d.state;
+    const int64_t n = st->step;
+    const int64_t h = n % d.hist_cap;
+    d.hist[2 * h] = fx;
+    d.hist[2 * h + 1] = fy;
+    if (n >= d.lockin_first && n < d.lockin_first + d.lockin_count) {
+      const Drive dr = d.drive[n];
+      st->lockin[0] += fx * dr.s;
+      st->lockin[1] += fx * dr.c;
+      st->lockin[2] += fx;
+      st->lockin[3] += fy * dr.s;
+      st->lockin[4] += fy * dr.c;
+      st->lockin[5] += fy;
+    }
+    st->step = n + 1;
+  }
+}
+
+template <class L, typename S, bool BGK>
+static hipError_t launch_step_t(const SolveDesc* descs, const WorkItem* work, int nwork,
+                                const KernelLattice& lat, hipStream_t stream) {
+  hipLaunchKernelGGL((step_kernel<L, S, BGK>), dim3(nwork), dim3(kBlock), 0, stream, descs,
+                     work, lat);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(int Q, bool f64, bool bgk, const SolveDesc* descs, const WorkItem* work,
+                       int nwork, const KernelLattice& lat, hipStream_t stream) {
+  if (nwork <= 0) return hipSuccess;
+  if (Q == 9) {
+    if (f64) return bgk ? launch_step_t<D2Q9, double, true>(descs, work, nwork, lat, stream)
+                        : launch_step_t<D2Q9, double, false>(descs, work, nwork, lat, stream);
+    return bgk ? launch_step_t<D2Q9, float, true>(descs, work, nwork, lat, stream)
+               : launch_step_t<D2Q9, float, false>(descs, work, nwork, lat, stream);
+  }
+  if (f64) return bgk ? launch_step_t<D2Q37, double, true>(descs, work, nwork, lat, stream)
+                      : launch_step_t<D2Q37, double, false>(descs, work, nwork, lat, stream);
+  return bgk ? launch_step_t<D2Q37, float, true>(descs, work, nwork, lat, stream)
+             : launch_step_t<D2Q37, float, false>(descs, work, nwork, lat, stream);
+}
+
+hipError_t launch_finalize(const SolveDesc* descs, const int32_t* solves, int nsolves,
+                           hipStream_t stream) {
+  if (nsolves <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(nsolves), dim3(kBlock), 0, stream, descs, solves);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,67 @@
+// Internal data structures shared by the kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
+constexpr int kMaxSlots = 1 << 20;
+
+enum Geom : int32_t { GEOM_PLATE = 0, GEOM_BOX = 1, GEOM_PERIODIC = 2 };
+enum Far : int32_t { FAR_WALL = 0, FAR_EQ = 1 };
+
+// Per-step drive sample: wall velocity and lock-in basis at t_n = n + 1/2.
+struct Drive {
+  double u;    // U_w(t_n) = u0 sin(omega t_n)
+  double s;    // sin(omega t_n)
+  double c;    // cos(omega t_n)
+};
+
+// Device-resident counters and accumulators of one solve.
+struct SolveState {
+  int64_t step;        // steps completed; selects the input buffer (parity) and drive[step]
+  int32_t unstable;    // set by the step kernel when a cell has rho <= 0 or non-finite
+  int32_t pad;
+  double lockin[6];    // x: sum F sin, sum F cos, sum F; then the same for y
+};
+
+// Everything a kernel needs to advance one solve; lives in device memory.
+// Pointers are device addresses.
+struct SolveDesc {
+  void* buf[2];              // population planes A, B: [Q][ny][pitch] + plane padding
+  const Drive* drive;        // [max_steps]
+  double* hist;              // force ring [hist_cap][2]
+  SolveState* state;
+  double* partials;          // [nslots][2] per-tile force partial sums
+  const int32_t* slot;       // [ntiles] tile -> partial slot, -1 if the tile has no wall link
+  int64_t plane;             // elements between planes
+  int64_t max_steps;
+  int64_t hist_cap;
+  int64_t lockin_first, lockin_count;
+  int32_t nx, ny, pitch, ncells;   // ncells = nx * ny (row-major cell index y*nx + x)
+  int32_t geom, far;
+  int32_t bx0, by0, bx1, by1;      // solid cells [bx0,bx1) x [by0,by1) (box only)
+  int32_t ntiles, nslots;
+  int32_t cells_per_tile;
+  int32_t pad0;
+  double inv_tau;                  // 1/tau (0 for tau = +inf)
+  double rho0;
+  double ladd_scale;               // 2 rho0 / theta: moving-wall term per unit (w_i v_i.U)
+  double fstatic[2];               // rest-state part of the wall force (geometry constant)
+};
+
+// One entry of the launch work list: a tile of one solve.
+struct WorkItem {
+  int32_t solve;
+  int32_t tile;
+};
+
+// Lattice constants passed by value to the kernels.
+struct KernelLattice {
+  double w[8];        // weights per orbit
+  double theta;
+};
+
+}  // namespace lbm

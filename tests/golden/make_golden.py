@@ -1,0 +1,93 @@
+"""Write the stored oracle results used by the GPU parity tests.
+
+Calls only the CPU oracle (and the seeded workload definitions).  Each case
+is written to tests/golden/<case>.json with the workload parameters, the
+lock-in fit (a, b, c, R, X) and the force series sampled every `stride`
+steps plus the last 64 steps in full.
+
+  python tests/golden/make_golden.py stokes_plate          # D2Q9 4x256, 160 850 steps
+  python tests/golden/make_golden.py plate_sweep           # D2Q37 4x2048, 5 tau*omega
+  python tests/golden/make_golden.py beam_box [tw ...]     # D2Q37 1024^2 box, hours
+  options: --threads N
+"""
+import argparse
+import dataclasses
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import lbm_inputs as W  # noqa: E402
+import oracle as O  # noqa: E402
+
+
+def oracle_params(s, threads):
+    return O.OracleParams(
+        Q=s.Q, nx=s.nx, ny=s.ny, tau=s.tau, omega=s.omega, u0=s.u0, rho0=s.rho0,
+        geometry={W.PLATE: O.GEOM_PLATE, W.BOX: O.GEOM_BOX, W.PERIODIC: O.GEOM_PERIODIC}[s.geometry],
+        far=O.FAR_WALL if s.far == W.FAR_WALL else O.FAR_EQ,
+        collision=O.COLL_REGULARIZED if s.collision == "regularized" else O.COLL_BGK,
+        box_x0=s.box[0], box_y0=s.box[1], box_lx=s.box[2], box_ly=s.box[3], nthreads=threads)
+
+
+def run_case(s, variant, threads, stride):
+    p = oracle_params(s, threads)
+    v, w, th = O.lattice(s.Q, variant)
+    f0 = None
+    if s.noise:
+        f0 = w[:, None, None] * s.rho0 + W.initial_noise(s)
+    t0 = time.time()
+    fx, fy, _ = O.run(p, s.nsteps, f0=f0, variant=variant)
+    dt = time.time() - t0
+    z = O.lockin_fit(fx, s.window_first, s.window_count, s.omega, s.u0)
+    zy = O.lockin_fit(fy, s.window_first, s.window_count, s.omega, s.u0)
+    idx = sorted(set(range(0, s.nsteps, stride)) | set(range(max(0, s.nsteps - 64), s.nsteps)))
+    return {
+        "solve": {k: (list(v) if isinstance(v, tuple) else v)
+                  for k, v in dataclasses.asdict(s).items()},
+        "variant": variant,
+        "seconds": dt,
+        "threads": threads,
+        "fit": {k: z[k] for k in ("a", "b", "c", "R", "X")},
+        "fit_y": {k: zy[k] for k in ("a", "b", "c")},
+        "max_abs_fx": float(np.max(np.abs(fx))),
+        "max_abs_fy": float(np.max(np.abs(fy))),
+        "samples": {"step": idx, "fx": [float(fx[i]) for i in idx],
+                    "fy": [float(fy[i]) for i in idx]},
+    }
+
+
+def write(name, obj):
+    path = os.path.join(HERE, name + ".json")
+    with open(path, "w") as fh:
+        json.dump(obj, fh, indent=1)
+    print("wrote", path, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("case", choices=["stokes_plate", "plate_sweep", "beam_box"])
+    ap.add_argument("tau_omega", nargs="*", type=float)
+    ap.add_argument("--threads", type=int, default=0)
+    a = ap.parse_args()
+    if a.case == "stokes_plate":
+        s = W.stokes_plate()
+        out = {"f64": run_case(s, "f64", a.threads, 101), "ld": run_case(s, "ld", a.threads, 101)}
+        write("stokes_plate", out)
+    elif a.case == "plate_sweep":
+        for tw in a.tau_omega or W.PLATE_SWEEP_TAU_OMEGA:
+            s = W.plate_sweep(tw, storage="f64")
+            write(f"plate_sweep_tw{tw:g}", run_case(s, "f64", a.threads, 97))
+    else:
+        for tw in a.tau_omega or W.BEAM_TAU_OMEGA:
+            s = W.beam_box(tw, storage="f64")
+            write(f"beam_box_tw{tw:g}", run_case(s, "f64", a.threads, 97))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/lbm.h declares, its lattice constants agree with the
+oracle's independently derived ones, and parameter validation behaves."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import lbm_inputs as W
+import oracle as O
+import paper_0904_4504_amd as P
+from paper_0904_4504_amd import lbm as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [s for s in _declared() if s not in exported]
+    assert not missing, missing
+    lib = P.lib()
+    for s in _declared():
+        assert hasattr(lib, s)
+
+
+def test_header_is_plain_c_and_struct_layout_matches_binding():
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "lbm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(lbm_params), offsetof(lbm_params, tau),
+         offsetof(lbm_params, max_steps), offsetof(lbm_params, history_capacity),
+         offsetof(lbm_params, box_ly));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        c, "-o", exe], check=True)
+        got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
+                                              check=True).stdout.split()]
+    expect = [C.sizeof(B.Params), B.Params.tau.offset, B.Params.max_steps.offset,
+              B.Params.history_capacity.offset, B.Params.box_ly.offset]
+    assert got == expect
+
+
+@pytest.mark.parametrize("Q", [9, 37])
+def test_library_lattice_matches_oracle(Q):
+    v, w, th = P.lattice(Q)
+    vo, wo, tho = O.lattice(Q, "ld")
+    assert np.array_equal(v, vo)
+    assert np.max(np.abs(w / wo - 1)) <= 2.3e-16
+    assert abs(th / tho - 1) <= 2.3e-16
+
+
+def test_lattice_rejects_unknown_q():
+    with pytest.raises(P.LbmError) as e:
+        P.lattice(19)
+    assert e.value.code == B.EINVAL
+
+
+def _plate(**kw):
+    p = P.params_from_solve(W.plate_sweep(1.0, ny=64).scaled(100, 50))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _box(**kw):
+    p = P.params_from_solve(W.beam_box(1.0, n=128).scaled(100, 50))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("make,kw,code", [
+    (_plate, {"tau": 0.5}, B.EINVAL),
+    (_plate, {"tau": float("nan")}, B.EINVAL),
+    (_plate, {"nx": 2}, B.EINVAL),
+    (_plate, {"lattice": 19}, B.EINVAL),
+    (_plate, {"storage": 7}, B.EINVAL),
+    (_plate, {"abi_version": 99}, B.EABI),
+    (_plate, {"rho0": 0.0}, B.EINVAL),
+    (_plate, {"max_steps": 0}, B.EINVAL),
+    (_plate, {"lockin_first": 60, "lockin_count": 50}, B.EINVAL),
+    (_plate, {"history_capacity": 101}, B.EINVAL),
+    (_box, {"far": B.FAR_WALL}, B.EINVAL),
+    (_box, {"box_x0": 2}, B.EINVAL),
+    (_box, {"box_lx": 2}, B.EINVAL),
+    (_box, {"box_x0": 128 - 32 - 2}, B.EINVAL),
+])
+def test_required_bytes_validation(make, kw, code):
+    with pytest.raises(P.LbmError) as e:
+        P.required_bytes(make(**kw))
+    assert e.value.code == code
+
+
+def test_required_bytes_sizes():
+    p = _box()
+    n = P.required_bytes(p)
+    cells = 128 * 128
+    assert n >= 2 * 37 * cells * 4
+    assert n < 2 * 37 * cells * 4 * 1.2 + 1e6
+    p.storage = B.STORE_F64
+    assert P.required_bytes(p) >= 2 * 37 * cells * 8
+    p.tau = float("inf")
+    P.required_bytes(p)
+
+
+def test_beam_box_fits_one_gpu_with_room():
+    p = P.params_from_solve(W.beam_box(1.0))
+    assert P.required_bytes(p) < 0.4e9
+
+
+def test_strerror():
+    for code in (B.OK, B.EINVAL, B.ENOMEM, B.EHIP, B.ERANGE, B.EUNSTABLE, B.EABI):
+        assert P.strerror(code) and P.strerror(code) != "unknown error"
+    assert P.strerror(-99) == "unknown error"
+
+
+def test_solver_needs_a_gpu_here():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        P.Solver(_plate())

@@ -1,0 +1,394 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (FP64 storage: 1e-12 relative on forces and impedance, T1 of the
+design; FP32 deviation storage: 1e-4 relative on |Z| and 1e-4 rad on the
+phase, and a per-step bound derived from FP32 rounding for short runs).
+The oracle is run live on small cases; the full-size workloads compare with
+stored oracle results in tests/golden (written by make_golden.py).
+"""
+import cmath
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import lbm_inputs as W
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0904_4504_amd as P
+    return P
+
+
+def _oracle_params(s, threads=0):
+    return O.OracleParams(
+        Q=s.Q, nx=s.nx, ny=s.ny, tau=s.tau, omega=s.omega, u0=s.u0, rho0=s.rho0,
+        geometry={W.PLATE: O.GEOM_PLATE, W.BOX: O.GEOM_BOX, W.PERIODIC: O.GEOM_PERIODIC}[s.geometry],
+        far=O.FAR_WALL if s.far == W.FAR_WALL else O.FAR_EQ,
+        collision=O.COLL_REGULARIZED if s.collision == "regularized" else O.COLL_BGK,
+        box_x0=s.box[0], box_y0=s.box[1], box_lx=s.box[2], box_ly=s.box[3], nthreads=threads)
+
+
+def _gpu(P, s, f0=None, state=False, memory="torch", history_capacity=0):
+    p = P.params_from_solve(s, history_capacity)
+    with P.Solver(p, memory=memory) as sv:
+        if f0 is not None:
+            sv.set_populations(f0)
+        sv.step(s.nsteps)
+        sv.synchronize()
+        cap = history_capacity or s.nsteps
+        fx, fy = sv.force_history(s.nsteps - cap, cap)
+        z = sv.impedance() if s.window_count >= 3 else None
+        f = sv.get_populations() if state else None
+    return fx, fy, z, f
+
+
+def _f0(s, w, seed, amp):
+    """Rest state plus a seeded perturbation (relative amplitude amp)."""
+    f = w[:, None, None] * s.rho0 * (1 + W.random_state(s.Q, s.ny, s.nx, seed, amp))
+    if s.geometry == W.BOX:
+        x0, y0, lx, ly = s.box
+        f[:, y0:y0 + ly, x0:x0 + lx] = 0.0
+    return f
+
+
+SMALL = {
+    # name: (Q, geometry, far, collision, nx, ny, box, tau)
+    "q9_plate_wall_narrow": (9, W.PLATE, W.FAR_WALL, "regularized", 5, 300, (0, 0, 0, 0), 0.8),
+    "q9_plate_eq_wide": (9, W.PLATE, W.FAR_EQ, "regularized", 70, 41, (0, 0, 0, 0), 0.6),
+    "q9_box": (9, W.BOX, W.FAR_EQ, "regularized", 70, 45, (20, 15, 12, 9), 0.9),
+    "q9_periodic_bgk": (9, W.PERIODIC, W.FAR_EQ, "bgk", 33, 29, (0, 0, 0, 0), 0.7),
+    "q37_plate_wall_narrow": (37, W.PLATE, W.FAR_WALL, "regularized", 4, 333, (0, 0, 0, 0), 2.0),
+    "q37_plate_eq_wide": (37, W.PLATE, W.FAR_EQ, "regularized", 67, 40, (0, 0, 0, 0), 0.7),
+    "q37_box": (37, W.BOX, W.FAR_EQ, "regularized", 71, 47, (21, 15, 13, 10), 1.3),
+    "q37_box_bgk": (37, W.BOX, W.FAR_EQ, "bgk", 64, 40, (20, 14, 6, 5), 0.8),
+    "q37_periodic": (37, W.PERIODIC, W.FAR_EQ, "regularized", 31, 37, (0, 0, 0, 0), 5.0),
+    "q37_plate_large_tau": (37, W.PLATE, W.FAR_WALL, "regularized", 4, 260, (0, 0, 0, 0), 16298.0),
+}
+
+
+def _small_solve(name, storage, nsteps=40):
+    Q, geom, far, coll, nx, ny, box, tau = SMALL[name]
+    om = 2 * math.pi / 32
+    return W.Solve(Q=Q, geometry=geom, far=far, nx=nx, ny=ny, tau=tau, omega=om, u0=1e-3,
+                   box=box, nsteps=nsteps, window_first=8, window_count=nsteps - 8,
+                   storage=storage, collision=coll, name=name)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("name", list(SMALL))
+def test_small_parity(P, name, storage):
+    """Populations after 40 steps and every per-step force, element by element."""
+    s = _small_solve(name, storage)
+    print(f"case {name} {storage} {s.nx}x{s.ny}", flush=True)
+    v, w, th = P.lattice(s.Q)
+    f0 = _f0(s, w, seed=hash(name) % 1000, amp=1e-3)
+    fx, fy, z, f = _gpu(P, s, f0, state=True)
+    ox, oy, of = O.run(_oracle_params(s), s.nsteps, f0=f0, want_state=True, variant="ld")
+    wo = O.lattice(s.Q, "ld")[1]
+    dev_o = of - wo[:, None, None] * s.rho0
+    dev_g = f - w[:, None, None] * s.rho0
+    if s.geometry == W.BOX:
+        x0, y0, lx, ly = s.box
+        dev_o[:, y0:y0 + ly, x0:x0 + lx] = 0
+        dev_g[:, y0:y0 + ly, x0:x0 + lx] = 0
+    scale = np.max(np.abs(dev_o))
+    tol_pop, tol_f = (1e-12, 1e-12) if storage == "f64" else (2e-5, 2e-5)
+    # populations cross the ABI as full f in FP64: one rounding of each side
+    # at the magnitude of w_i rho0 is the floor of this comparison
+    floor = 2 * np.spacing(np.max(w) * s.rho0)
+    assert np.max(np.abs(dev_g - dev_o)) <= tol_pop * scale + floor
+    if s.geometry != W.PERIODIC:
+        fscale = max(np.max(np.abs(ox)), np.max(np.abs(oy)))
+        assert np.max(np.abs(fx - ox)) <= tol_f * fscale
+        assert np.max(np.abs(fy - oy)) <= tol_f * fscale
+        zo = O.lockin_fit(ox, s.window_first, s.window_count, s.omega, s.u0)
+        assert abs(z["Z"] - zo["Z"]) <= (1e-11 if storage == "f64" else 1e-4) * abs(zo["Z"])
+
+
+@pytest.mark.parametrize("Q", [9, 37])
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_first_step_and_free_molecular_limit(P, Q, storage):
+    """Closed forms: from rest F_0 = -2 rho0 U_w(1/2) nx C_s; with free
+    streaming (BGK, tau = inf) and an open far field F_n = -2 rho0 C_s nx U_w
+    at every step (eq. free-molecular, BB = 2 x DS)."""
+    v, w, th = P.lattice(Q)
+    C_s = sum(w[i] * abs(v[i, 1]) * v[i, 0] ** 2 / th for i in range(Q) if v[i, 1] < 0)
+    om = 2 * math.pi / 64
+    s = W.Solve(Q=Q, geometry=W.PLATE, far=W.FAR_EQ, nx=300, ny=40, tau=float("inf"),
+                omega=om, u0=1e-3, nsteps=256, window_first=64, window_count=192,
+                storage=storage, collision="bgk")
+    fx, fy, z, _ = _gpu(P, s)
+    U = 1e-3 * np.sin(om * (np.arange(256) + 0.5))
+    expect = -2 * C_s * s.nx * U
+    tol = 1e-13 if storage == "f64" else 2e-7
+    assert np.max(np.abs(fx - expect)) <= tol * np.max(np.abs(expect))
+    assert z["R"] / s.nx == pytest.approx(2 * C_s, rel=10 * tol)
+    assert abs(z["X"] / s.nx) <= 10 * tol
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result {name}")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _cmp_samples(fx, g, tol, key="fx"):
+    steps = np.array(g["samples"]["step"])
+    ref = np.array(g["samples"][key])
+    scale = g["max_abs_fx"]
+    err = np.max(np.abs(fx[steps] - ref)) / scale
+    assert err <= tol, err
+    return err
+
+
+def test_stokes_plate_full_fp64(P):
+    """D2Q9 FP64, 4 x 256, 160 850 steps with seeded noise: every sampled force
+    and the impedance within 1e-12 of the long-double oracle."""
+    g = _golden("stokes_plate")["ld"]
+    s = W.stokes_plate()
+    v, w, th = P.lattice(9)
+    f0 = w[:, None, None] * s.rho0 + W.initial_noise(s)
+    fx, fy, z, _ = _gpu(P, s, f0)
+    _cmp_samples(fx, g, 1e-12)
+    assert z["R"] == pytest.approx(g["fit"]["R"], rel=1e-12)
+    assert z["X"] == pytest.approx(g["fit"]["X"], rel=1e-12)
+    Zs = (1 + 1j) * math.sqrt(0.1 * s.omega / 2)
+    assert abs(abs(z["Z"] / s.nx) / abs(Zs) - 1) < 1e-2
+
+
+@pytest.mark.parametrize("tw", W.PLATE_SWEEP_TAU_OMEGA)
+def test_plate_sweep_full(P, tw):
+    """D2Q37, 4 x 2048, 30 periods: FP32-deviation storage within 1e-4 on |Z|
+    and 1e-4 rad on the phase of the FP64 oracle; FP64 storage within 1e-12."""
+    g = _golden(f"plate_sweep_tw{tw:g}")
+    Zo = complex(g["fit"]["R"], g["fit"]["X"])
+    for storage in ("f32dev", "f64"):
+        s = W.plate_sweep(tw, storage=storage)
+        fx, fy, z, _ = _gpu(P, s)
+        print(f"tw={tw} {storage} Z={z['Z']} oracle={Zo}", flush=True)
+        if storage == "f64":
+            assert abs(z["Z"] - Zo) <= 1e-12 * abs(Zo)
+            _cmp_samples(fx, g, 1e-11)
+        else:
+            assert abs(abs(z["Z"]) / abs(Zo) - 1) <= 1e-4
+            assert abs(cmath.phase(z["Z"]) - cmath.phase(Zo)) <= 1e-4
+
+
+@pytest.mark.parametrize("tw", W.BEAM_TAU_OMEGA)
+def test_beam_box_full(P, tw):
+    """D2Q37 FP32 deviation storage, 1024^2 with a 32 x 16 body, 20 480 steps:
+    impedance within 1e-4 (|Z|) and 1e-4 rad of the FP64 oracle; the body is
+    y-symmetric so the lift stays at rounding level."""
+    g = _golden(f"beam_box_tw{tw:g}")
+    Zo = complex(g["fit"]["R"], g["fit"]["X"])
+    s = W.beam_box(tw)
+    fx, fy, z, _ = _gpu(P, s)
+    print(f"tw={tw} Z={z['Z']} oracle={Zo}", flush=True)
+    assert abs(abs(z["Z"]) / abs(Zo) - 1) <= 1e-4
+    assert abs(cmath.phase(z["Z"]) - cmath.phase(Zo)) <= 1e-4
+    _cmp_samples(fx, g, 1e-3)
+    assert np.max(np.abs(fy)) <= 1e-5 * np.max(np.abs(fx))
+
+
+# ------------------------------------------------------------------ behaviour
+
+def test_deterministic_and_memory_owner_independent(P):
+    s = _small_solve("q37_box", "f32dev", nsteps=30)
+    a = _gpu(P, s, state=True, memory="torch")
+    b = _gpu(P, s, state=True, memory="library")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_checkpoint_resume(P, storage):
+    """Run 40 steps straight, versus 20 steps -> checkpoint (populations +
+    lock-in sums) -> a new solver seeks to step 20 -> 20 more steps."""
+    s = _small_solve("q37_plate_wall_narrow", storage, nsteps=40)
+    v, w, th = P.lattice(s.Q)
+    f0 = _f0(s, w, 5, 1e-3)
+    fx, fy, z, fend = _gpu(P, s, f0, state=True)
+    p = P.params_from_solve(s)
+    with P.Solver(p) as a:
+        a.set_populations(f0)
+        a.step(20)
+        mid = a.get_deviations()
+        sums, _ = a.lockin()
+    with P.Solver(p) as b:
+        b.seek(20, sums)
+        b.set_deviations(mid)
+        b.step(20)
+        fx2, _ = b.force_history(20, 20)
+        z2 = b.impedance()
+        f2 = b.get_populations()
+        with pytest.raises(P.LbmError):
+            b.force_history(19, 2)
+    assert np.array_equal(fx2, fx[20:])
+    assert np.array_equal(f2, fend)
+    assert z2["Z"] == z["Z"]
+
+
+def test_unstable_state_is_reported(P):
+    s = _small_solve("q9_periodic_bgk", "f64", nsteps=10)
+    p = P.params_from_solve(s)
+    v, w, th = P.lattice(9)
+    f0 = _f0(s, w, 1, 1e-3)
+    f0[3, 5, 7] = np.nan
+    with P.Solver(p) as sv:
+        sv.set_populations(f0)
+        sv.step(2)
+        with pytest.raises(P.LbmError) as e:
+            sv.synchronize()
+        assert e.value.code == -5
+        sv.get_populations()  # still readable
+
+
+def test_range_errors_and_history_ring(P):
+    s = _small_solve("q9_plate_wall_narrow", "f64", nsteps=50)
+    full = _gpu(P, s)[0]
+    p = P.params_from_solve(s, history_capacity=16)
+    with P.Solver(p) as sv:
+        with pytest.raises(P.LbmError) as e:
+            sv.step(51)
+        assert e.value.code == -4
+        sv.step(50)
+        fx, _ = sv.force_history(34, 16)
+        assert np.array_equal(fx, full[34:])
+        with pytest.raises(P.LbmError) as e:
+            sv.force_history(33, 2)
+        assert e.value.code == -4
+        with pytest.raises(P.LbmError):
+            sv.step(1)
+
+
+def test_lockin_sums_match_force_series(P):
+    s = _small_solve("q37_box", "f64", nsteps=60)
+    p = P.params_from_solve(s)
+    with P.Solver(p) as sv:
+        sv.step(60)
+        fx, fy = sv.force_history(0, 60)
+        sums, n = sv.lockin()
+    assert n == s.window_count
+    t = np.arange(s.window_first, s.window_first + s.window_count) + 0.5
+    sn, cs = np.sin(s.omega * t), np.cos(s.omega * t)
+    wx = fx[s.window_first:]
+    assert sums[0] == pytest.approx(np.dot(wx, sn), rel=1e-12)
+    assert sums[1] == pytest.approx(np.dot(wx, cs), rel=1e-12)
+    assert sums[2] == pytest.approx(wx.sum(), rel=1e-12, abs=1e-18)
+
+
+def test_periodic_mass_and_momentum_conserved(P):
+    s = _small_solve("q37_periodic", "f64", nsteps=25)
+    v, w, th = P.lattice(37)
+    f0 = _f0(s, w, 9, 1e-2)
+    _, _, _, f = _gpu(P, s, f0, state=True)
+    assert abs(f.sum() - f0.sum()) <= 1e-13 * f0.sum()
+    j0 = np.einsum("qyx,qa->a", f0, v.astype(float))
+    j1 = np.einsum("qyx,qa->a", f, v.astype(float))
+    assert np.max(np.abs(j1 - j0)) <= 1e-13 * f0.sum()
+
+
+# ------------------------------------------------------------------ batching
+
+def _mix(storage="f32dev"):
+    om = 2 * math.pi / 40
+    return [
+        W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=90, ny=70, tau=0.9, omega=om,
+                box=(30, 25, 20, 12), nsteps=60, window_first=20, window_count=40,
+                storage=storage, name="box"),
+        W.Solve(Q=37, geometry=W.PLATE, far=W.FAR_WALL, nx=4, ny=700, tau=3.0, omega=om,
+                nsteps=45, window_first=5, window_count=40, storage=storage, name="plate"),
+        W.Solve(Q=37, geometry=W.PLATE, far=W.FAR_EQ, nx=130, ny=50, tau=0.55, omega=om,
+                nsteps=70, window_first=30, window_count=40, storage=storage, name="wide"),
+    ]
+
+
+def _alone(P, s, stream):
+    with P.Solver(P.params_from_solve(s), stream=stream) as sv:
+        sv.step(s.nsteps)
+        fx, fy = sv.force_history(0, s.nsteps)
+        return fx, fy, sv.get_populations()
+
+
+@pytest.mark.parametrize("graphs", [0, 8])
+def test_batch_alone_equals_mix(P, graphs):
+    """Uneven lattices in one fused launch, one member joining late and one
+    finishing early: every member's forces and populations are bit-identical
+    to the same solve stepped alone."""
+    import torch
+    stream = torch.cuda.Stream()
+    solves = _mix()
+    ref = [_alone(P, s, stream) for s in solves]
+    svs = [P.Solver(P.params_from_solve(s), stream=stream) for s in solves]
+    b = P.Batch(stream)
+    b.set_graphs(graphs)
+    b.add(svs[0])
+    b.add(svs[1])
+    b.step(10)
+    b.add(svs[2])                 # joins at its own step 0
+    b.step(100)                   # plate stops at 45, box at 60, wide after 70 of its own
+    assert b.size() == (3, 0)
+    b.synchronize()
+    for s, sv, (rx, ry, rf) in zip(solves, svs, ref):
+        fx, fy = sv.force_history(0, s.nsteps)
+        assert np.array_equal(fx, rx) and np.array_equal(fy, ry), s.name
+        assert np.array_equal(sv.get_populations(), rf), s.name
+    b.close()
+    for sv in svs:
+        sv.close()
+
+
+def test_graph_replays_match_eager(P):
+    """Replays of the captured graph, with eager work and synchronisation
+    between them, each agree with plain launches."""
+    import torch
+    stream = torch.cuda.Stream()
+    s = _mix()[0].scaled(64, 40)
+    with P.Solver(P.params_from_solve(s), stream=stream) as ref:
+        ref.step(64)
+        rx, _ = ref.force_history(0, 64)
+    with P.Solver(P.params_from_solve(s), stream=stream) as sv:
+        b = P.Batch(stream)
+        b.add(sv)
+        b.set_graphs(16)
+        for r in range(4):
+            b.step(16)
+            with torch.cuda.stream(stream):
+                junk = torch.ones(1000, device="cuda") * r   # eager work between replays
+            b.synchronize()
+            fx, _ = sv.force_history(16 * r, 16)
+            assert np.array_equal(fx, rx[16 * r:16 * (r + 1)]), r
+            del junk
+        b.close()
+
+
+def test_batch_rejects_mismatched_members(P):
+    import torch
+    stream = torch.cuda.Stream()
+    a = _mix("f32dev")[0]
+    c = _mix("f64")[0]
+    sa = P.Solver(P.params_from_solve(a), stream=stream)
+    sc = P.Solver(P.params_from_solve(c), stream=stream)
+    sd = P.Solver(P.params_from_solve(a), stream=torch.cuda.Stream())
+    b = P.Batch(stream)
+    b.add(sa)
+    for bad in (sc, sd, sa):
+        with pytest.raises(P.LbmError):
+            b.add(bad)
+    b.close()
+    for sv in (sa, sc, sd):
+        sv.close()
