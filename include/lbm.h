@@ -92,6 +92,9 @@ typedef struct lbm_params {
   uint32_t wall;         /* LBM_WALL_BB */
   uint32_t geometry;     /* LBM_GEOM_* */
   uint32_t far;          /* LBM_FAR_* */
+  uint32_t tile;         /* tile of the fused kernel: 0 (= 1), 1, 2 or 4; one workgroup of
+                            256*tile threads updates 256*tile consecutive cells, one per
+                            thread.  Batch members must agree. */
   int32_t nx, ny;        /* domain in cells; nx >= 3 and ny >= 3 */
   int32_t box_x0, box_y0, box_lx, box_ly; /* BOX only; sides and margins >= longest link */
   double tau;            /* relaxation time of the update, > 1/2; +inf allowed (BGK: free streaming) */

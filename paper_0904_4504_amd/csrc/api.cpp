@@ -42,6 +42,7 @@ int validate(const lbm_params* p, HostLattice* lat) {
   if (p->collision != LBM_COLL_REGULARIZED && p->collision != LBM_COLL_BGK) return LBM_EINVAL;
   if (p->wall != LBM_WALL_BB) return LBM_EINVAL;
   if (p->far != LBM_FAR_WALL && p->far != LBM_FAR_EQ) return LBM_EINVAL;
+  if (p->tile != 0 && p->tile != 1 && p->tile != 2 && p->tile != 4) return LBM_EINVAL;
   const int R = lat->R;
   if (p->nx < std::max(3, R) || p->ny < std::max(3, R)) return LBM_EINVAL;
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) return LBM_EINVAL;
@@ -125,6 +126,8 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   // Q concurrent plane streams do not all map to the same HBM channel
   lay->plane = (int64_t)align_up((uint64_t)p->ny * lay->pitch, 256) + 256;
   const int64_t ncells = (int64_t)p->nx * p->ny;
+  lay->cpt = p->tile ? (int32_t)p->tile : 1;
+  lay->cells_per_tile = kBlock * lay->cpt;
   lay->ntiles = (int32_t)((ncells + lay->cells_per_tile - 1) / lay->cells_per_tile);
   lay->hist_cap = p->history_capacity ? p->history_capacity : p->max_steps;
   uint64_t o = 0;
@@ -356,8 +359,8 @@ int lbm_step(lbm_solver* s, int64_t nsteps) {
   const bool f64 = s->p.storage == LBM_STORE_F64;
   const bool bgk = s->p.collision == LBM_COLL_BGK;
   for (int64_t k = 0; k < nsteps; ++k) {
-    if (launch_step((int)s->p.lattice, f64, bgk, s->d_desc, s->d_work, s->lay.ntiles, s->klat,
-                    s->stream) != hipSuccess)
+    if (launch_step((int)s->p.lattice, f64, bgk, s->lay.cpt, s->d_desc, s->d_work,
+                    s->lay.ntiles, s->klat, s->stream) != hipSuccess)
       return LBM_EHIP;
     if (launch_finalize(s->d_desc, s->d_solves, 1, s->stream) != hipSuccess) return LBM_EHIP;
     ++s->steps;

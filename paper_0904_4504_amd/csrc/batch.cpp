@@ -19,6 +19,7 @@ struct lbm_batch {
   std::vector<lbm_solver*> members;
   int Q = 0;
   uint32_t storage = 0, collision = 0;
+  int cpt = 1;
   // current launch set (members that still have steps to run)
   std::vector<lbm_solver*> active;
   bool dirty = true;
@@ -131,10 +132,10 @@ int launch_one(lbm_batch* b) {
     hipEvent_t e0 = next_event(b), e1 = next_event(b);
     if (!e0 || !e1) return LBM_EHIP;
     if (hipEventRecord(e0, b->stream) != hipSuccess) return LBM_EHIP;
-    if (launch_step(b->Q, f64, bgk, b->d_descs, b->d_work, b->nwork, lat, b->stream) != hipSuccess)
+    if (launch_step(b->Q, f64, bgk, b->cpt, b->d_descs, b->d_work, b->nwork, lat, b->stream) != hipSuccess)
       return LBM_EHIP;
     if (hipEventRecord(e1, b->stream) != hipSuccess) return LBM_EHIP;
-  } else if (launch_step(b->Q, f64, bgk, b->d_descs, b->d_work, b->nwork, lat, b->stream) !=
+  } else if (launch_step(b->Q, f64, bgk, b->cpt, b->d_descs, b->d_work, b->nwork, lat, b->stream) !=
              hipSuccess) {
     return LBM_EHIP;
   }
@@ -194,8 +195,9 @@ int lbm_batch_add(lbm_batch* b, lbm_solver* s) {
     b->Q = (int)s->p.lattice;
     b->storage = s->p.storage;
     b->collision = s->p.collision;
+    b->cpt = s->lay.cpt;
   } else if ((int)s->p.lattice != b->Q || s->p.storage != b->storage ||
-             s->p.collision != b->collision) {
+             s->p.collision != b->collision || s->lay.cpt != b->cpt) {
     return LBM_EINVAL;
   }
   b->members.push_back(s);

@@ -11,8 +11,9 @@
 
 namespace lbm {
 
-hipError_t launch_step(int Q, bool f64, bool bgk, const SolveDesc* descs, const WorkItem* work,
-                       int nwork, const KernelLattice& lat, hipStream_t stream);
+hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, const SolveDesc* descs,
+                       const WorkItem* work, int nwork, const KernelLattice& lat,
+                       hipStream_t stream);
 hipError_t launch_finalize(const SolveDesc* descs, const int32_t* solves, int nsolves,
                            hipStream_t stream);
 
@@ -32,7 +33,7 @@ struct HostLattice {
 // Where every region lives inside the one device allocation.
 struct Layout {
   int64_t pitch = 0, plane = 0;
-  int32_t ntiles = 0, nslots = 0, cells_per_tile = kBlock;
+  int32_t ntiles = 0, nslots = 0, cells_per_tile = kBlock, cpt = 1;
   int64_t hist_cap = 0;
   uint64_t off_desc = 0, off_state = 0, off_work = 0, off_solves = 0, off_slot = 0,
            off_part = 0, off_drive = 0, off_hist = 0, off_buf[2] = {0, 0};

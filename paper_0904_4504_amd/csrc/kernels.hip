@@ -120,20 +120,15 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
   return fin[q * plane + (int64_t)sy * pitch + sx];
 }
 
+// Update of one cell: pull, moments, collision, store; adds the cell's wall
+// force contribution to (fx, fy).
 template <class L, typename S, bool BGK>
-__global__ __launch_bounds__(kBlock) void step_kernel(const SolveDesc* __restrict__ descs,
-                                                      const WorkItem* __restrict__ work,
-                                                      KernelLattice lat) {
+__device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restrict__ fin,
+                                            S* __restrict__ fout, int64_t n, int c,
+                                            const KernelLattice& lat, double& fx, double& fy) {
   constexpr int Q = L::Q, R = L::R;
-  const WorkItem wi = work[xcd_remap(blockIdx.x, gridDim.x)];
-  const SolveDesc& d = descs[wi.solve];
-  const int64_t n = d.state->step;
-  const S* __restrict__ fin = static_cast<const S*>(d.buf[n & 1]);
-  S* __restrict__ fout = static_cast<S*>(d.buf[(n & 1) ^ 1]);
   const int nx = d.nx, ny = d.ny, pitch = d.pitch;
   const int64_t plane = d.plane;
-
-  const int c = wi.tile * d.cells_per_tile + (int)threadIdx.x;
   const bool active = c < d.ncells;
   const int y = active ? c / nx : 0;
   const int x = active ? c - y * nx : 0;
@@ -146,12 +141,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const SolveDesc* __restric
   const int64_t idx = (int64_t)y * pitch + x;
 
   S f[Q];
-  double fx = 0.0, fy = 0.0;
   if (fluid && interior) {
     static_for<0, Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      constexpr int off = 0;  // keeps the offset expression below in int64
-      f[q] = fin[q * plane + idx - ((int64_t)L::vy[q] * pitch + L::vx[q]) + off];
+      f[q] = fin[q * plane + idx - ((int64_t)L::vy[q] * pitch + L::vx[q])];
     });
   } else if (fluid) {
     const double ladd = d.ladd_scale * d.drive[n].u;
@@ -195,40 +188,51 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const SolveDesc* __restric
     const S a0 = drho - (bxx + byy) * (S(0.5) * inv_th);
     const S bx = jx * inv_th, by = jy * inv_th;
     const S cxx = bxx * h2, cxy = bxy * (S(2) * h2), cyy = byy * h2;
-    if (fluid) {
-      static_for<0, Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr int vx = L::vx[q], vy = L::vy[q];
-        S p = a0;
-        if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
-        if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
-        if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
-        fout[q * plane + idx] = (S)lat.w[L::orbit[q]] * p;
-      });
-    }
+    if (fluid) static_for<0, Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int vx = L::vx[q], vy = L::vy[q];
+      S p = a0;
+      if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
+      if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
+      if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
+      fout[q * plane + idx] = (S)lat.w[L::orbit[q]] * p;
+    });
   } else {
     // plain BGK: delta f^post = delta f + omega_r (delta f^eq - delta f)
     const S a0 = drho - (uxx + uyy) * (S(0.5) * inv_th);
     const S bx = jx * inv_th, by = jy * inv_th;
     const S cxx = uxx * h2, cxy = uxy * (S(2) * h2), cyy = uyy * h2;
-    if (fluid) {
-      static_for<0, Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr int vx = L::vx[q], vy = L::vy[q];
-        S p = a0;
-        if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
-        if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
-        if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
-        const S feq = (S)lat.w[L::orbit[q]] * p;
-        fout[q * plane + idx] = f[q] + om * (feq - f[q]);
-      });
-    }
+    if (fluid) static_for<0, Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int vx = L::vx[q], vy = L::vy[q];
+      S p = a0;
+      if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
+      if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
+      if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
+      const S feq = (S)lat.w[L::orbit[q]] * p;
+      fout[q * plane + idx] = f[q] + om * (feq - f[q]);
+    });
   }
+}
+
+// One workgroup of BS threads per tile of BS consecutive cells (row-major),
+// one cell per thread.
+template <class L, typename S, bool BGK, int BS>
+__global__ __launch_bounds__(BS) void step_kernel(const SolveDesc* __restrict__ descs,
+                                                  const WorkItem* __restrict__ work,
+                                                  KernelLattice lat) {
+  const WorkItem wi = work[xcd_remap(blockIdx.x, gridDim.x)];
+  const SolveDesc& d = descs[wi.solve];
+  const int64_t n = d.state->step;
+  const S* __restrict__ fin = static_cast<const S*>(d.buf[n & 1]);
+  S* __restrict__ fout = static_cast<S*>(d.buf[(n & 1) ^ 1]);
+  double fx = 0.0, fy = 0.0;
+  update_cell<L, S, BGK>(d, fin, fout, n, wi.tile * BS + (int)threadIdx.x, lat, fx, fy);
 
   // per-tile force partial (fixed reduction order: lanes, then waves)
   const int slot = d.slot[wi.tile];
   if (slot >= 0) {
-    __shared__ double red[2][kBlock / 64];
+    __shared__ double red[2][BS / 64];
     fx = wave_sum(fx);
     fy = wave_sum(fy);
     const int wave = threadIdx.x >> 6;
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const SolveDesc* __restric
     if (threadIdx.x == 0) {
       double sx = 0.0, sy = 0.0;
 #pragma unroll
-      for (int k = 0; k < kBlock / 64; ++k) {
+      for (int k = 0; k < BS / 64; ++k) {
         sx += red[0][k];
         sy += red[1][k];
       }
@@ -300,26 +304,41 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __res
 }
 
 template <class L, typename S, bool BGK>
-static hipError_t launch_step_t(const SolveDesc* descs, const WorkItem* work, int nwork,
+static hipError_t launch_step_t(int cpt, const SolveDesc* descs, const WorkItem* work, int nwork,
                                 const KernelLattice& lat, hipStream_t stream) {
-  hipLaunchKernelGGL((step_kernel<L, S, BGK>), dim3(nwork), dim3(kBlock), 0, stream, descs,
-                     work, lat);
+  switch (cpt) {
+    case 1:
+      hipLaunchKernelGGL((step_kernel<L, S, BGK, kBlock>), dim3(nwork), dim3(kBlock), 0, stream,
+                         descs, work, lat);
+      break;
+    case 2:
+      hipLaunchKernelGGL((step_kernel<L, S, BGK, 2 * kBlock>), dim3(nwork), dim3(2 * kBlock), 0,
+                         stream, descs, work, lat);
+      break;
+    case 4:
+      hipLaunchKernelGGL((step_kernel<L, S, BGK, 4 * kBlock>), dim3(nwork), dim3(4 * kBlock), 0,
+                         stream, descs, work, lat);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_step(int Q, bool f64, bool bgk, const SolveDesc* descs, const WorkItem* work,
-                       int nwork, const KernelLattice& lat, hipStream_t stream) {
+hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, const SolveDesc* descs,
+                       const WorkItem* work, int nwork, const KernelLattice& lat,
+                       hipStream_t stream) {
   if (nwork <= 0) return hipSuccess;
   if (Q == 9) {
-    if (f64) return bgk ? launch_step_t<D2Q9, double, true>(descs, work, nwork, lat, stream)
-                        : launch_step_t<D2Q9, double, false>(descs, work, nwork, lat, stream);
-    return bgk ? launch_step_t<D2Q9, float, true>(descs, work, nwork, lat, stream)
-               : launch_step_t<D2Q9, float, false>(descs, work, nwork, lat, stream);
+    if (f64) return bgk ? launch_step_t<D2Q9, double, true>(cpt, descs, work, nwork, lat, stream)
+                        : launch_step_t<D2Q9, double, false>(cpt, descs, work, nwork, lat, stream);
+    return bgk ? launch_step_t<D2Q9, float, true>(cpt, descs, work, nwork, lat, stream)
+               : launch_step_t<D2Q9, float, false>(cpt, descs, work, nwork, lat, stream);
   }
-  if (f64) return bgk ? launch_step_t<D2Q37, double, true>(descs, work, nwork, lat, stream)
-                      : launch_step_t<D2Q37, double, false>(descs, work, nwork, lat, stream);
-  return bgk ? launch_step_t<D2Q37, float, true>(descs, work, nwork, lat, stream)
-             : launch_step_t<D2Q37, float, false>(descs, work, nwork, lat, stream);
+  if (f64) return bgk ? launch_step_t<D2Q37, double, true>(cpt, descs, work, nwork, lat, stream)
+                      : launch_step_t<D2Q37, double, false>(cpt, descs, work, nwork, lat, stream);
+  return bgk ? launch_step_t<D2Q37, float, true>(cpt, descs, work, nwork, lat, stream)
+             : launch_step_t<D2Q37, float, false>(cpt, descs, work, nwork, lat, stream);
 }
 
 hipError_t launch_finalize(const SolveDesc* descs, const int32_t* solves, int nsolves,

@@ -42,7 +42,7 @@ class Params(C.Structure):
     _fields_ = [
         ("abi_version", C.c_uint32), ("lattice", C.c_uint32), ("storage", C.c_uint32),
         ("collision", C.c_uint32), ("wall", C.c_uint32), ("geometry", C.c_uint32),
-        ("far", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("far", C.c_uint32), ("tile", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
         ("box_x0", C.c_int32), ("box_y0", C.c_int32), ("box_lx", C.c_int32),
         ("box_ly", C.c_int32), ("tau", C.c_double), ("omega", C.c_double),
         ("u0", C.c_double), ("rho0", C.c_double), ("max_steps", C.c_int64),
@@ -124,9 +124,10 @@ def default_params():
     return p
 
 
-def params_from_solve(s, history_capacity=0):
+def params_from_solve(s, history_capacity=0, tile=0):
     """lbm_params for an lbm_inputs.Solve."""
     p = default_params()
+    p.tile = tile
     p.lattice = s.Q
     p.storage = STORE_F64 if s.storage == "f64" else STORE_F32_DEV
     p.collision = COLL_REGULARIZED if s.collision == "regularized" else COLL_BGK

@@ -392,3 +392,53 @@ def test_batch_rejects_mismatched_members(P):
     b.close()
     for sv in (sa, sc, sd):
         sv.close()
+
+
+# ------------------------------------------------------------------ serving
+
+def test_serving_results_same_alone_and_in_mix(P):
+    """Requests arriving while others run are admitted as memory frees up (a
+    budget of about two requests forces queueing), advance together in the
+    running batch, and each impedance equals the same solve run alone."""
+    import torch
+    from paper_0904_4504_amd import serve
+    om = 2 * math.pi / 64
+    trace = []
+    for k in range(7):
+        if k % 3 == 0:
+            s = W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=96 + 8 * k, ny=80, tau=0.7 + 0.3 * k,
+                        omega=om, box=(40, 32, 16, 10), nsteps=320 + 32 * k, window_first=128,
+                        window_count=192 + 32 * k, name=f"box{k}")
+        else:
+            s = W.Solve(Q=37, geometry=W.PLATE, far=W.FAR_WALL, nx=4, ny=500 + 100 * k,
+                        tau=0.6 + 2.0 * k, omega=om, nsteps=256 + 64 * k, window_first=64,
+                        window_count=192 + 64 * k, name=f"plate{k}")
+        trace.append((0.005 * k, s))
+    stream = torch.cuda.Stream()
+    need = sorted(P.required_bytes(P.params_from_solve(s)) for _, s in trace)
+    reqs, summ = serve.serve(trace, budget_bytes=need[-1] + need[-2] + 2048, chunk=48,
+                             stream=stream)
+    assert summ["requests"] == 7
+    assert any(r.admitted > r.arrival + 1e-4 for r in reqs)   # someone had to wait
+    for r in reqs:
+        with P.Solver(P.params_from_solve(r.solve), stream=stream) as sv:
+            sv.step(r.solve.nsteps)
+            z = sv.impedance()
+        assert r.result["Z"] == z["Z"], r.solve.name
+
+
+@pytest.mark.parametrize("name,storage", [("q37_box", "f32dev"), ("q9_plate_eq_wide", "f64"),
+                                          ("q37_plate_wall_narrow", "f64")])
+def test_tile_variants_agree(P, name, storage):
+    """Cells per thread 1, 2, 4: identical populations; forces differ only by
+    the order of the tile partial sums."""
+    s = _small_solve(name, storage, nsteps=30)
+    out = []
+    for tile in (1, 2, 4):
+        with P.Solver(P.params_from_solve(s, tile=tile)) as sv:
+            sv.step(s.nsteps)
+            fx, fy = sv.force_history(0, s.nsteps)
+            out.append((fx, sv.get_populations()))
+    for fx, f in out[1:]:
+        assert np.array_equal(f, out[0][1])
+        assert np.max(np.abs(fx - out[0][0])) <= 1e-14 * np.max(np.abs(out[0][0]))
