@@ -36,6 +36,11 @@
  *   - Force on the body (momentum exchange) F = -sum_links v_i (f_opp(x_p) + f_i^adv(x)).
  *   - Far field: stationary half-way bounce-back at y = ny - 1/2 (plate), or
  *     rest-equilibrium ghost populations w_i rho0 outside the domain.
+ *   - Diffuse scattering (eq. DS) at the plate: a population arriving from the
+ *     wall in column x is the H2 equilibrium at the wall velocity and the wall
+ *     density rho_w(x); rho_w(x) balances the mass of the populations of
+ *     column x that cross the wall in this step (zero normal mass flux, eq.
+ *     kinetic_bc), the crossing links counted as in bounce-back.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -56,6 +61,7 @@ typedef ORACLE_REAL real;
 enum { ORC_GEOM_PLATE = 0, ORC_GEOM_BOX = 1, ORC_GEOM_PERIODIC = 2 };
 enum { ORC_FAR_WALL = 0, ORC_FAR_EQ = 1 };
 enum { ORC_COLL_REGULARIZED = 0, ORC_COLL_BGK = 1 };
+enum { ORC_WALL_BB = 0, ORC_WALL_DS = 1 };
 
 typedef struct {
   int Q;          /* 9 or 37 */
@@ -69,6 +75,7 @@ typedef struct {
   double u0;      /* drive amplitude: U_w(t) = u0 sin(omega t) along x */
   double rho0;    /* rest density */
   int nthreads;   /* OpenMP threads, 0 = runtime default */
+  int wall;       /* ORC_WALL_*: model of the moving wall (DS: plate only) */
 } oracle_params;
 
 typedef struct {
@@ -125,19 +132,20 @@ static int in_body(const oracle_params* p, int x, int y) {
 }
 
 static int check_params(const oracle_params* p, const lattice* L) {
+  const int m = vmax_of(L);
   if (p->nx < 1 || p->ny < 1) return -1;
   if (!(p->tau > 0.5)) return -1;
   if (p->geometry == ORC_GEOM_BOX) {
-    int m = vmax_of(L);
     if (p->box_lx < m || p->box_ly < m) return -1;
     if (p->box_x0 < m || p->box_y0 < m) return -1;
     if (p->box_x0 + p->box_lx + m > p->nx || p->box_y0 + p->box_ly + m > p->ny) return -1;
   } else if (p->geometry == ORC_GEOM_PLATE) {
-    if (p->ny < vmax_of(L)) return -1;
+    if (p->ny < m) return -1;
   } else if (p->geometry != ORC_GEOM_PERIODIC) {
     return -1;
   }
-  return 0;
+  if (p->wall == ORC_WALL_DS) return p->geometry == ORC_GEOM_PLATE ? 0 : -1;
+  return p->wall == ORC_WALL_BB ? 0 : -1;
 }
 
 /* Cell-major storage of the oracle's own: f[(y*nx + x)*Q + i]. */
@@ -147,8 +155,30 @@ static int check_params(const oracle_params* p, const lattice* L) {
 /* Advection of one population into fluid cell (x, y) along direction i
  * (eq. advection with the boundary rules above).  Adds the momentum-exchange
  * contribution of a moving-wall link to (*fx, *fy). */
+/* H2 equilibrium factor of direction i at velocity (U, 0), eq. feq_h2 / (w_i rho). */
+static real eq_factor(const lattice* L, int i, real U) {
+  const real vu = L->vx[i] * U, th = L->theta;
+  return 1 + vu / th + vu * vu / (2 * th * th) - U * U / (2 * th);
+}
+
+/* Diffuse-scattering wall density of every plate column: mass of the
+ * populations crossing the wall at y = -1/2 over the mass the wall emits per
+ * unit density, rho_w(x) = sum_cross f / sum_{v_y>0} v_y w eq_factor. */
+static void wall_density(const oracle_params* p, const lattice* L, const real* f, real U,
+                         real* rho_w) {
+  real emit = 0;
+  for (int i = 0; i < L->Q; ++i)
+    if (L->vy[i] > 0) emit += L->vy[i] * L->w[i] * eq_factor(L, i, U);
+  for (int x = 0; x < p->nx; ++x) {
+    real m = 0;
+    for (int i = 0; i < L->Q; ++i)
+      for (int r = 0; r < -L->vy[i]; ++r) m += F_AT(f, x, r, i);
+    rho_w[x] = m / emit;
+  }
+}
+
 static real advect_one(const oracle_params* p, const lattice* L, const real* f, int x, int y,
-                       int i, real U, real* fx, real* fy) {
+                       int i, real U, const real* rho_w, real* fx, real* fy) {
   const int vx = L->vx[i], vy = L->vy[i];
   int sx = x - vx, sy = y - vy;
   const real rest = L->w[i] * (real)p->rho0;
@@ -161,7 +191,8 @@ static real advect_one(const oracle_params* p, const lattice* L, const real* f, 
       /* crossed the moving wall at y = -1/2: retrace in y, keep x */
       int py = -1 - sy;
       real fr = F_AT(f, x, py, L->opp[i]);
-      real fa = fr + 2 * L->w[i] * (real)p->rho0 * (vx * U) / L->theta;
+      real fa = rho_w ? L->w[i] * rho_w[x] * eq_factor(L, i, U)
+                      : fr + 2 * L->w[i] * (real)p->rho0 * (vx * U) / L->theta;
       *fx -= vx * (fr + fa);
       *fy -= vy * (fr + fa);
       return fa;
@@ -309,6 +340,12 @@ int oracle_advect(const oracle_params* p, const double* f_in, double U, double* 
   if (load_lattice(p->Q, &L) || check_params(p, &L)) return -1;
   real* f = import_f(p, &L, f_in);
   if (!f) return -2;
+  real* rho_w = NULL;
+  if (p->wall == ORC_WALL_DS) {
+    rho_w = (real*)malloc(sizeof(real) * p->nx);
+    if (!rho_w) { free(f); return -2; }
+    wall_density(p, &L, f, (real)U, rho_w);
+  }
   real Fx = 0, Fy = 0;
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x)
@@ -318,11 +355,12 @@ int oracle_advect(const oracle_params* p, const double* f_in, double U, double* 
           f_adv[o] = 0;
           continue;
         }
-        f_adv[o] = (double)advect_one(p, &L, f, x, y, i, (real)U, &Fx, &Fy);
+        f_adv[o] = (double)advect_one(p, &L, f, x, y, i, (real)U, rho_w, &Fx, &Fy);
       }
   *fx = (double)Fx;
   *fy = (double)Fy;
   free(f);
+  free(rho_w);
   return 0;
 }
 
@@ -337,8 +375,9 @@ int oracle_run(const oracle_params* p, const double* f0, long nsteps, double* fx
   real* g = import_f(p, &L, NULL);
   real* rowfx = (real*)calloc((size_t)p->ny, sizeof(real));
   real* rowfy = (real*)calloc((size_t)p->ny, sizeof(real));
-  if (!f || !g || !rowfx || !rowfy) {
-    free(f); free(g); free(rowfx); free(rowfy);
+  real* rho_w = p->wall == ORC_WALL_DS ? (real*)calloc((size_t)p->nx, sizeof(real)) : NULL;
+  if (!f || !g || !rowfx || !rowfy || (p->wall == ORC_WALL_DS && !rho_w)) {
+    free(f); free(g); free(rowfx); free(rowfy); free(rho_w);
     return -2;
   }
   const real inv_tau = inv_tau_of(p->tau);
@@ -347,13 +386,14 @@ int oracle_run(const oracle_params* p, const double* f0, long nsteps, double* fx
 #endif
   for (long n = 0; n < nsteps; ++n) {
     const real U = (real)(p->u0 * sin(p->omega * ((double)n + 0.5)));
+    if (rho_w) wall_density(p, &L, f, U, rho_w);
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < p->ny; ++y) {
       real Fx = 0, Fy = 0;
       for (int x = 0; x < p->nx; ++x) {
         if (in_body(p, x, y)) continue;
         real fa[ORC_MAXQ], fo[ORC_MAXQ];
-        for (int i = 0; i < L.Q; ++i) fa[i] = advect_one(p, &L, f, x, y, i, U, &Fx, &Fy);
+        for (int i = 0; i < L.Q; ++i) fa[i] = advect_one(p, &L, f, x, y, i, U, rho_w, &Fx, &Fy);
         collide(&L, p->collision, inv_tau, fa, fo);
         for (int i = 0; i < L.Q; ++i) G_AT(g, x, y, i) = fo[i];
       }
@@ -372,7 +412,7 @@ int oracle_run(const oracle_params* p, const double* f0, long nsteps, double* fx
     g = t;
   }
   if (f_final) export_f(p, &L, f, f_final);
-  free(f); free(g); free(rowfx); free(rowfy);
+  free(f); free(g); free(rowfx); free(rowfy); free(rho_w);
   return 0;
 }
 

@@ -121,10 +121,22 @@ void plan_links(const lbm_params* p, const HostLattice& L, const Layout& lay,
 
 void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   const uint64_t es = p->storage == LBM_STORE_F64 ? 8 : 4;
-  lay->pitch = p->nx >= 64 ? (int64_t)align_up(p->nx, 64) : p->nx;
-  // planes start 256 elements past a 256-element boundary apart, so that the
-  // Q concurrent plane streams do not all map to the same HBM channel
-  lay->plane = (int64_t)align_up((uint64_t)p->ny * lay->pitch, 256) + 256;
+  if (p->nx >= 64) {
+    // row-interleaved: the Q rows of lattice row y are contiguous, so the Q
+    // streams of a workgroup touch a few contiguous rows of Q*pitch elements
+    lay->pitch = (int64_t)align_up(p->nx, 64);
+    lay->qs = lay->pitch;
+    lay->ys = (int64_t)L.Q * lay->pitch;
+    lay->buf_elems = lay->ys * p->ny;
+  } else {
+    // narrow lattices: whole-lattice planes (a wavefront covers several rows
+    // of one plane contiguously); planes start 256 elements past a
+    // 256-element boundary apart to spread them over HBM channels
+    lay->pitch = p->nx;
+    lay->qs = (int64_t)align_up((uint64_t)p->ny * lay->pitch, 256) + 256;
+    lay->ys = lay->pitch;
+    lay->buf_elems = lay->qs * L.Q;
+  }
   const int64_t ncells = (int64_t)p->nx * p->ny;
   lay->cpt = p->tile ? (int32_t)p->tile : 1;
   lay->cells_per_tile = kBlock * lay->cpt;
@@ -145,7 +157,7 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   lay->off_part = take(sizeof(double) * 2 * (uint64_t)lay->ntiles);
   lay->off_drive = take(sizeof(Drive) * (uint64_t)p->max_steps);
   lay->off_hist = take(sizeof(double) * 2 * (uint64_t)lay->hist_cap);
-  lay->buf_bytes = (uint64_t)L.Q * lay->plane * es;
+  lay->buf_bytes = (uint64_t)lay->buf_elems * es;
   o = align_up(o, 4096);
   lay->off_buf[0] = take(lay->buf_bytes);
   o = align_up(o, 4096);
@@ -177,14 +189,14 @@ int init_solver(lbm_solver* s) {
   d.state = reinterpret_cast<SolveState*>(b + lay.off_state);
   d.partials = reinterpret_cast<double*>(b + lay.off_part);
   d.slot = reinterpret_cast<const int32_t*>(b + lay.off_slot);
-  d.plane = lay.plane;
+  d.qs = lay.qs;
+  d.ys = lay.ys;
   d.max_steps = p->max_steps;
   d.hist_cap = lay.hist_cap;
   d.lockin_first = p->lockin_first;
   d.lockin_count = p->lockin_count;
   d.nx = p->nx;
   d.ny = p->ny;
-  d.pitch = (int32_t)lay.pitch;
   d.ncells = p->nx * p->ny;
   d.geom = (int32_t)p->geometry;
   d.far = (int32_t)p->far;
@@ -474,7 +486,7 @@ int copy_out(lbm_solver* s, double* host, uint64_t n, bool with_rest) {
     const double wr = with_rest ? s->lat.lw.w_orbit[s->lat.orbit[q]] * p.rho0 : 0.0;
     for (int y = 0; y < p.ny; ++y)
       for (int x = 0; x < p.nx; ++x) {
-        const int64_t src = q * s->lay.plane + (int64_t)y * s->lay.pitch + x;
+        const int64_t src = q * s->lay.qs + y * s->lay.ys + x;
         const double dv = f64 ? reinterpret_cast<const double*>(stage.data())[src]
                               : (double)reinterpret_cast<const float*>(stage.data())[src];
         host[((size_t)q * p.ny + y) * p.nx + x] = in_body(&p, x, y) ? 0.0 : wr + dv;
@@ -496,7 +508,7 @@ int copy_in(lbm_solver* s, const double* host, uint64_t n, bool with_rest) {
     const double wr = with_rest ? s->lat.lw.w_orbit[s->lat.orbit[q]] * p.rho0 : 0.0;
     for (int y = 0; y < p.ny; ++y)
       for (int x = 0; x < p.nx; ++x) {
-        const int64_t dst = q * s->lay.plane + (int64_t)y * s->lay.pitch + x;
+        const int64_t dst = q * s->lay.qs + y * s->lay.ys + x;
         const double dv = in_body(&p, x, y) ? 0.0 : host[((size_t)q * p.ny + y) * p.nx + x] - wr;
         if (f64) reinterpret_cast<double*>(stage.data())[dst] = dv;
         else reinterpret_cast<float*>(stage.data())[dst] = (float)dv;

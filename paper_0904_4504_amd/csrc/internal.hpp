@@ -32,7 +32,7 @@ struct HostLattice {
 
 // Where every region lives inside the one device allocation.
 struct Layout {
-  int64_t pitch = 0, plane = 0;
+  int64_t pitch = 0, qs = 0, ys = 0, buf_elems = 0;
   int32_t ntiles = 0, nslots = 0, cells_per_tile = kBlock, cpt = 1;
   int64_t hist_cap = 0;
   uint64_t off_desc = 0, off_state = 0, off_work = 0, off_solves = 0, off_slot = 0,

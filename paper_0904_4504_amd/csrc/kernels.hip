@@ -13,7 +13,10 @@
 // lock-in sums.
 //
 // Storage: deviations delta f_i = f_i - w_i rho0 in FP64 or FP32, structure
-// of arrays, plane q at buf + q*plane, cell (x, y) at y*pitch + x.  Written in
+// of arrays: population q of cell (x, y) at q*qs + y*ys + x.  Wide lattices
+// interleave the Q rows of each lattice row (qs = row pitch, ys = Q*pitch), so
+// the Q streams of a workgroup stay within a few hundred KB; narrow lattices
+// use whole-lattice planes (qs = plane, ys = nx).  Written in
 // deviation form the regularized collision needs only six sums of the pulled
 // populations (delta rho, j, P = sum delta f v v); its output is
 //   delta f_i^post = w_i [ a0 + v_i . b + c_xx vx^2 + c_xy vx vy + c_yy vy^2 ]
@@ -42,15 +45,6 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Remap so that consecutive tiles -- which share the misaligned edge
-// cache lines of the shifted pulls -- run on the same XCD.
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-  const int x = b & 7, l = b >> 3;
-  const int q = n >> 3, r = n & 7;
-  return x * q + (x < r ? x : r) + l;
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -66,15 +60,15 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
                                        int y, double ladd, double wq, double& fx, double& fy) {
   constexpr int vx = L::vx[q], vy = L::vy[q];
   constexpr int o = opposite<L>(q);
-  const int nx = d.nx, ny = d.ny, pitch = d.pitch;
-  const int64_t plane = d.plane;
+  const int nx = d.nx, ny = d.ny;
+  const int64_t qs = d.qs, ys = d.ys;
   int sx = x - vx, sy = y - vy;
   if (d.geom == GEOM_PERIODIC) {
     sx += sx < 0 ? nx : 0;
     sx -= sx >= nx ? nx : 0;
     sy += sy < 0 ? ny : 0;
     sy -= sy >= ny ? ny : 0;
-    return fin[q * plane + (int64_t)sy * pitch + sx];
+    return fin[q * qs + sy * ys + sx];
   }
   if (d.geom == GEOM_PLATE) {
     sx += sx < 0 ? nx : 0;
@@ -83,7 +77,7 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
       if (sy < 0) {
         // crossed the moving wall at y = -1/2: retrace in y, keep x
         const int py = -1 - sy;
-        const S fr = fin[o * plane + (int64_t)py * pitch + x];
+        const S fr = fin[o * qs + py * ys + x];
         const double lad = wq * vx * ladd;
         const double m = 2.0 * (double)fr + lad;
         fx -= vx * m;
@@ -95,10 +89,10 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
       if (sy >= ny) {
         if (d.far == FAR_EQ) return S(0);
         const int py = 2 * ny - 1 - sy;  // stationary wall at y = ny - 1/2
-        return fin[o * plane + (int64_t)py * pitch + x];
+        return fin[o * qs + py * ys + x];
       }
     }
-    return fin[q * plane + (int64_t)sy * pitch + sx];
+    return fin[q * qs + sy * ys + sx];
   }
   // box in a rest-equilibrium far field
   if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) return S(0);
@@ -110,14 +104,14 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
     else if (x >= d.bx1) px = 2 * d.bx1 - 1 - sx;
     if (y < d.by0) py = 2 * d.by0 - 1 - sy;
     else if (y >= d.by1) py = 2 * d.by1 - 1 - sy;
-    const S fr = fin[o * plane + (int64_t)py * pitch + px];
+    const S fr = fin[o * qs + py * ys + px];
     const double lad = wq * vx * ladd;
     const double m = 2.0 * (double)fr + lad;
     fx -= vx * m;
     fy -= vy * m;
     return fr + (S)lad;
   }
-  return fin[q * plane + (int64_t)sy * pitch + sx];
+  return fin[q * qs + sy * ys + sx];
 }
 
 // Update of one cell: pull, moments, collision, store; adds the cell's wall
@@ -127,8 +121,8 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
                                             S* __restrict__ fout, int64_t n, int c,
                                             const KernelLattice& lat, double& fx, double& fy) {
   constexpr int Q = L::Q, R = L::R;
-  const int nx = d.nx, ny = d.ny, pitch = d.pitch;
-  const int64_t plane = d.plane;
+  const int nx = d.nx, ny = d.ny;
+  const int64_t qs = d.qs, ys = d.ys;
   const bool active = c < d.ncells;
   const int y = active ? c / nx : 0;
   const int x = active ? c - y * nx : 0;
@@ -138,13 +132,13 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
   if (is_box) interior = interior && !(x >= d.bx0 - R && x < d.bx1 + R && y >= d.by0 - R &&
                                        y < d.by1 + R);
   const bool fluid = active && !solid;
-  const int64_t idx = (int64_t)y * pitch + x;
+  const int64_t idx = y * ys + x;
 
   S f[Q];
   if (fluid && interior) {
     static_for<0, Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      f[q] = fin[q * plane + idx - ((int64_t)L::vy[q] * pitch + L::vx[q])];
+      f[q] = fin[q * qs + idx - (L::vy[q] * ys + L::vx[q])];
     });
   } else if (fluid) {
     const double ladd = d.ladd_scale * d.drive[n].u;
@@ -195,7 +189,8 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
       if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
       if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
       if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
-      fout[q * plane + idx] = (S)lat.w[L::orbit[q]] * p;
+      // output is not re-read in this step: stream it past the caches
+      __builtin_nontemporal_store((S)lat.w[L::orbit[q]] * p, &fout[q * qs + idx]);
     });
   } else {
     // plain BGK: delta f^post = delta f + omega_r (delta f^eq - delta f)
@@ -210,7 +205,7 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
       if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
       if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
       const S feq = (S)lat.w[L::orbit[q]] * p;
-      fout[q * plane + idx] = f[q] + om * (feq - f[q]);
+      __builtin_nontemporal_store(f[q] + om * (feq - f[q]), &fout[q * qs + idx]);
     });
   }
 }
@@ -221,7 +216,11 @@ template <class L, typename S, bool BGK, int BS>
 __global__ __launch_bounds__(BS) void step_kernel(const SolveDesc* __restrict__ descs,
                                                   const WorkItem* __restrict__ work,
                                                   KernelLattice lat) {
-  const WorkItem wi = work[xcd_remap(blockIdx.x, gridDim.x)];
+  // Workgroups take their tiles in launch order (no XCD remapping): with
+  // row-interleaved storage the whole GPU then streams through one compact
+  // region of HBM at a time, which measured faster than giving each XCD its
+  // own band of rows.
+  const WorkItem wi = work[blockIdx.x];
   const SolveDesc& d = descs[wi.solve];
   const int64_t n = d.state->step;
   const S* __restrict__ fin = static_cast<const S*>(d.buf[n & 1]);

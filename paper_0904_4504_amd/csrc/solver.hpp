@@ -30,17 +30,18 @@ struct SolveState {
 // Everything a kernel needs to advance one solve; lives in device memory.
 // Pointers are device addresses.
 struct SolveDesc {
-  void* buf[2];              // population planes A, B: [Q][ny][pitch] + plane padding
+  void* buf[2];              // populations A, B: population q of cell (x, y) at q*qs + y*ys + x
   const Drive* drive;        // [max_steps]
   double* hist;              // force ring [hist_cap][2]
   SolveState* state;
   double* partials;          // [nslots][2] per-tile force partial sums
   const int32_t* slot;       // [ntiles] tile -> partial slot, -1 if the tile has no wall link
-  int64_t plane;             // elements between planes
+  int64_t qs;                // elements between the populations of one cell
+  int64_t ys;                // elements between rows
   int64_t max_steps;
   int64_t hist_cap;
   int64_t lockin_first, lockin_count;
-  int32_t nx, ny, pitch, ncells;   // ncells = nx * ny (row-major cell index y*nx + x)
+  int32_t nx, ny, ncells, pad1;    // ncells = nx * ny (row-major cell index y*nx + x)
   int32_t geom, far;
   int32_t bx0, by0, bx1, by1;      // solid cells [bx0,bx1) x [by0,by1) (box only)
   int32_t ntiles, nslots;

@@ -33,8 +33,10 @@ def _reflect_box(p, d, box):
     return tuple(a)
 
 
-def stream(f, v, w, theta, geometry, far, box, U, rho0):
-    """Push streaming.  Returns (f_adv, Fx, Fy); f is [q][y][x]."""
+def stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse=False):
+    """Push streaming.  Returns (f_adv, Fx, Fy); f is [q][y][x].  With
+    diffuse=True the plate wall re-emits what hits it as the H2 equilibrium at
+    the wall velocity, at the density that returns the column's mass."""
     Q, ny, nx = f.shape
     opp = [int(np.flatnonzero((v[:, 0] == -v[i, 0]) & (v[:, 1] == -v[i, 1]))[0]) for i in range(Q)]
     fadv = np.full_like(f, np.nan)
@@ -46,6 +48,18 @@ def stream(f, v, w, theta, geometry, far, box, U, rho0):
         x0, y0, lx, ly = box
         return x0 <= x < x0 + lx and y0 <= y < y0 + ly
 
+    # diffuse plate wall: mass hitting the wall per column, and emitted shape
+    hit = np.zeros(nx)
+    emitted = {}
+    if diffuse:
+        for q in range(Q):
+            for y in range(ny):
+                if y + v[q, 1] < 0:
+                    hit += f[q, y, :]
+        vu = v[:, 0] * U
+        eq = 1 + vu / theta + vu ** 2 / (2 * theta ** 2) - U ** 2 / (2 * theta)
+        per_rho = sum(v[i, 1] * w[i] * eq[i] for i in range(Q) if v[i, 1] > 0)
+        rho_w = hit / per_rho
     for q in range(Q):
         ux, uy = int(v[q, 0]), int(v[q, 1])
         for y in range(ny):
@@ -60,7 +74,10 @@ def stream(f, v, w, theta, geometry, far, box, U, rho0):
                         # bounces on the moving wall; arrives with velocity -u
                         i = opp[q]
                         ax, ay = x, -1 - dy
-                        out = val + 2 * w[i] * rho0 * (v[i, 0] * U) / theta
+                        if diffuse:
+                            out = w[i] * rho_w[x] * eq[i]
+                        else:
+                            out = val + 2 * w[i] * rho0 * (v[i, 0] * U) / theta
                         fadv[i, ay, ax] = out
                         Fx += -v[i, 0] * (val + out)
                         Fy += -v[i, 1] * (val + out)
@@ -116,8 +133,8 @@ def collide(fadv, v, w, theta, tau, regularized=True):
     return feq + keep * fne
 
 
-def step(f, v, w, theta, tau, geometry, far, box, U, rho0=1.0, regularized=True):
-    fadv, Fx, Fy = stream(f, v, w, theta, geometry, far, box, U, rho0)
+def step(f, v, w, theta, tau, geometry, far, box, U, rho0=1.0, regularized=True, diffuse=False):
+    fadv, Fx, Fy = stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse)
     out = collide(fadv, v, w, theta, tau, regularized)
     if geometry == "box":
         x0, y0, lx, ly = box

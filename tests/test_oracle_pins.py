@@ -468,3 +468,88 @@ def test_double_oracle_rounding_floor():
     zld, fld = _plate_Z(s, "ld")
     assert np.max(np.abs(f64 - fld)) <= 1e-10 * np.max(np.abs(fld))
     assert abs(z64["Z"] - zld["Z"]) <= 1e-11 * abs(zld["Z"])
+
+
+# ---------------------------------------------------------------- diffuse scattering
+
+def _ds_emission(v, w, th, U):
+    """Mass the plate wall emits per unit wall density, per column: sum over
+    v_y > 0 of v_y w eq_factor(U) (v_y arrival rows per direction)."""
+    vu = v[:, 0] * U
+    eq = 1 + vu / th + vu ** 2 / (2 * th ** 2) - U ** 2 / (2 * th)
+    return sum(v[i, 1] * w[i] * eq[i] for i in range(len(w)) if v[i, 1] > 0)
+
+
+@pytest.mark.parametrize("Q", [9, 37])
+def test_diffuse_free_molecular_is_half_bounce_back(Q):
+    """Eq. free-molecular: F^DS = F^BB / 2.  With free streaming and an open
+    far field the wall only ever meets rest populations, so every step the
+    diffuse wall re-emits the incoming mass at velocity U_w:
+    F_n = -rho0 C_s nx U_w * W1 / E(U_w), W1 = sum_{v_y>0} v_y w_i, E the
+    emitted mass per unit density -- half of bounce-back up to O(U^2)."""
+    v, w, th = O.lattice(Q, "ld")
+    om, u0, nx = 2 * math.pi / 64, 1e-3, 6
+    p = O.OracleParams(Q=Q, nx=nx, ny=24, far=O.FAR_EQ, collision=O.COLL_BGK, tau=INF,
+                       omega=om, u0=u0, wall=O.WALL_DS)
+    n = 128
+    fx, fy, _ = O.run(p, n, variant="ld")
+    U = u0 * np.sin(om * (np.arange(n) + 0.5))
+    W1 = sum(v[i, 1] * w[i] for i in range(Q) if v[i, 1] > 0)
+    E = np.array([_ds_emission(v, w, th, u) for u in U])
+    expect = -_C_s(v, w, th) * nx * U * W1 / E
+    assert np.max(np.abs(fx - expect)) <= 1e-13 * np.max(np.abs(expect))
+    p.wall = O.WALL_BB
+    fbb, _, _ = O.run(p, n, variant="ld")
+    assert np.max(np.abs(fx / fbb - 0.5)) < 1e-6
+
+
+@pytest.mark.parametrize("Q", [9, 37])
+def test_diffuse_wall_conserves_mass_in_closed_channel(Q):
+    v, w, th = O.lattice(Q, "ld")
+    p = O.OracleParams(Q=Q, nx=5, ny=20, tau=0.9, omega=0.3, u0=0.01, far=O.FAR_WALL,
+                       wall=O.WALL_DS)
+    f0 = w[:, None, None] * (1 + W.random_state(Q, 20, 5, seed=4, amp=0.01))
+    _, _, f = O.run(p, 30, f0=f0, want_state=True, variant="ld")
+    assert abs(f.sum() - f0.sum()) <= 1e-14 * f0.sum()
+
+
+@pytest.mark.parametrize("Q", [9, 37])
+@pytest.mark.parametrize("far", ["wall", "eq"])
+def test_diffuse_one_step_matches_brute_force(Q, far):
+    v, w, th = O.lattice(Q, "ld")
+    nx, ny, tau, U = 4, 9, 0.83, 4e-3
+    f = w[:, None, None] * (1 + W.random_state(Q, ny, nx, seed=Q + 3, amp=0.02))
+    ref, Fx, Fy = brute_lbm.step(f, v, w, th, tau, "plate", far, (0, 0, 0, 0), U, 1.0, True,
+                                 diffuse=True)
+    p = O.OracleParams(Q=Q, nx=nx, ny=ny, tau=tau, omega=math.pi, u0=U,
+                       far=O.FAR_WALL if far == "wall" else O.FAR_EQ, wall=O.WALL_DS)
+    fx, fy, fin = O.run(p, 1, f0=f, want_state=True, variant="ld")
+    assert np.max(np.abs(fin - ref)) <= 1e-15
+    assert abs(fx[0] - Fx) <= 1e-14 * max(abs(Fx), 1e-3)
+    assert abs(fy[0] - Fy) <= 1e-14 * max(abs(Fy), 1e-3)
+
+
+def test_diffuse_wall_slip_reduces_damping():
+    """The diffuse wall lets the gas slip (Sec. 4: sigma_v = 1 versus the
+    no-slip bounce-back), so its damping lies below bounce-back's: equal as
+    tau*omega -> 0 (no slip in the Newtonian limit) and falling through the
+    transition towards the free-molecular ratio 1/2."""
+    ratio = {}
+    for tw in (0.01, 0.1, 1.0):
+        om = 2 * math.pi / 256
+        base = dict(Q=37, nx=4, ny=160, tau=tw / om + 0.5, omega=om, u0=1e-3, nthreads=2)
+        zs = []
+        for wall in (O.WALL_BB, O.WALL_DS):
+            fx, _, _ = O.run(O.OracleParams(**base, wall=wall), 1536)
+            zs.append(O.lockin_fit(fx, 768, 768, om, 1e-3))
+        ratio[tw] = zs[1]["R"] / zs[0]["R"]
+    assert 0.95 < ratio[0.01] < 1.0
+    assert ratio[1.0] < ratio[0.1] < ratio[0.01]
+    assert ratio[1.0] > 0.3
+
+
+def test_diffuse_wall_rejected_for_box():
+    p = O.OracleParams(Q=9, geometry=O.GEOM_BOX, far=O.FAR_EQ, nx=20, ny=20, box_x0=5,
+                       box_y0=5, box_lx=5, box_ly=5, wall=O.WALL_DS)
+    with pytest.raises(ValueError):
+        O.run(p, 1)
