@@ -30,12 +30,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("MLUPS & HBM GB/s (%peak); sweep solves/s + p50/p99 latency vs plain loop")
 HBM_PEAK_GBS = 8000.0
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "step_kernel_beam_box_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_0904_4504_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_0904_4504_amd", "csrc")
+# dominant kernel per device representation: (name, source file, counters file)
+KERNELS = {
+    1: ("lbm::step_kernel<D2Q37, float, false, 256, false>", "kernels.hip",
+        "step_kernel_beam_box_counters.json"),
+    2: ("lbm::moment_kernel<D2Q37, float>", "moments.hip", "moment_kernel_beam_box_counters.json"),
+}
 
 
-def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
+def kernel_hash(src):
+    with open(os.path.join(CSRC, src), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
@@ -58,15 +63,16 @@ def workload(name, steps, warmup):
     return solves, desc
 
 
-def traffic_from_profile(launch_bytes_alg):
+def traffic_from_profile(repr_):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
     taken on the current kernel source; else None."""
+    _, src, counters = KERNELS[repr_]
     try:
-        with open(PROFILE_COUNTERS) as fh:
+        with open(os.path.join(ROOT, "profiles", counters)) as fh:
             prof = json.load(fh)
     except (OSError, ValueError):
         return None
-    if prof.get("kernel_source_sha256_16") != kernel_hash():
+    if prof.get("kernel_source_sha256_16") != kernel_hash(src):
         return None
     return prof.get("hbm_bytes_per_launch")
 
@@ -103,6 +109,8 @@ def main():
     ap.add_argument("--workload", default="beam_box")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--representation", type=int, default=0,
+                    help="0 automatic, 1 populations, 2 H2 coefficients")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solves of a sweep are independent and would "
@@ -117,7 +125,9 @@ def main():
     solves, desc = workload(a.workload, a.steps, a.warmup)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        solvers = [P.Solver(P.params_from_solve(s), stream=stream) for s in solves]
+        solvers = [P.Solver(P.params_from_solve(s, representation=a.representation),
+                            stream=stream) for s in solves]
+        repr_ = solvers[0].representation
         batch = P.Batch(stream)
         for sv in solvers:
             batch.add(sv)
@@ -141,12 +151,14 @@ def main():
 
     cells = sum(s.fluid_cells for s in solves)
     Q = solves[0].Q
-    bytes_per_lu = 2 * Q * 4
+    # algorithmic bytes per lattice update: read and write the stored state once
+    # (Q populations, or the six H2 coefficients of the regularized state)
+    bytes_per_lu = 2 * (Q if repr_ == 1 else 6) * 4
     mlups = cells * a.steps / (elapsed_ms / 1e3) / 1e6
     avg_kernel_s = kern_ms / 1e3 / launches
     launch_bytes = bytes_per_lu * cells
     achieved = launch_bytes / avg_kernel_s / 1e9
-    traffic = traffic_from_profile(launch_bytes)
+    traffic = traffic_from_profile(repr_)
     out = {
         "metric": METRIC,
         "value": mlups,
@@ -166,11 +178,12 @@ def main():
             "solves": len(solves),
             "fluid_cells": cells,
             "algorithmic_bytes_per_update": bytes_per_lu,
+            "representation": {1: "populations", 2: "H2 coefficients"}[repr_],
             "force_and_lockin": "f64",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "lbm::step_kernel<D2Q37, float, false>",
+            "kernel": KERNELS[repr_][0],
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

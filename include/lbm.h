@@ -84,6 +84,15 @@ enum { LBM_GEOM_PLATE = 0, LBM_GEOM_BOX = 1, LBM_GEOM_PERIODIC = 2 };
  * rest-equilibrium ghost populations w_i rho0. */
 enum { LBM_FAR_WALL = 0, LBM_FAR_EQ = 1 };
 
+/* Device representation of the state.  The regularized collision (eqs.
+ * regularization, fne) leaves every post-collision distribution in the span
+ * of the Hermite polynomials up to second order, so six coefficients per
+ * cell describe it exactly; a step then moves 6 values per cell in and out of
+ * HBM instead of Q.  After populations are loaded (lbm_set_populations /
+ * lbm_set_deviations) the next step reads them directly, so an arbitrary
+ * initial state is honoured exactly. */
+enum { LBM_REPR_AUTO = 0, LBM_REPR_POPULATIONS = 1, LBM_REPR_COEFFICIENTS = 2 };
+
 typedef struct lbm_params {
   uint32_t abi_version;  /* LBM_ABI_VERSION */
   uint32_t lattice;      /* LBM_D2Q9 or LBM_D2Q37 */
@@ -95,6 +104,9 @@ typedef struct lbm_params {
   uint32_t tile;         /* tile of the fused kernel: 0 (= 1), 1, 2 or 4; one workgroup of
                             256*tile threads updates 256*tile consecutive cells, one per
                             thread.  Batch members must agree. */
+  uint32_t representation; /* device state: 0 = automatic, 1 = the Q populations, 2 = the six
+                            H2 coefficients of the regularized post-collision state
+                            (regularized collision only; automatic picks 2 when nx >= 64) */
   int32_t nx, ny;        /* domain in cells; nx >= 3 and ny >= 3 */
   int32_t box_x0, box_y0, box_lx, box_ly; /* BOX only; sides and margins >= longest link */
   double tau;            /* relaxation time of the update, > 1/2; +inf allowed (BGK: free streaming) */
@@ -142,6 +154,10 @@ int lbm_step(lbm_solver* s, int64_t nsteps);
  * lbm_get_populations and lbm_destroy). */
 int lbm_synchronize(lbm_solver* s);
 
+/* Representation the solver keeps on the device (LBM_REPR_POPULATIONS or
+ * LBM_REPR_COEFFICIENTS). */
+int lbm_representation(const lbm_solver* s, int* repr);
+
 /* Steps enqueued so far (host-side count; no wait). */
 int lbm_steps_done(const lbm_solver* s, int64_t* n);
 
@@ -171,17 +187,25 @@ int lbm_impedance(lbm_solver* s, double out[5]);
 int lbm_get_populations(lbm_solver* s, double* host, uint64_t n);
 int lbm_set_populations(lbm_solver* s, const double* host, uint64_t n);
 
-/* The same for the stored deviations f - w_i rho0 (FP64 on the host for
- * both storages), so that a round trip is bit-exact. */
+/* The same for the deviations f - w_i rho0 (FP64 on the host for both
+ * storages).  With the population representation a round trip is bit-exact;
+ * with coefficients, reading rebuilds the populations from them. */
 int lbm_get_deviations(lbm_solver* s, double* host, uint64_t n);
 int lbm_set_deviations(lbm_solver* s, const double* host, uint64_t n);
 
+/* Raw device state (representation header + the current buffer), for
+ * bit-exact checkpoints in either representation.  lbm_state_size gives the
+ * byte count; lbm_set_state accepts only a blob taken from a solver with the
+ * same parameters.  Both wait for the stream. */
+int lbm_state_size(const lbm_solver* s, uint64_t* bytes);
+int lbm_get_state(lbm_solver* s, void* host, uint64_t bytes);
+int lbm_set_state(lbm_solver* s, const void* host, uint64_t bytes);
+
 /* Move the solver to step n (0 <= n < max_steps) with the given lock-in
- * sums (NULL = zeros).  The current populations become those of step n;
- * force history before n is no longer available.  Together with
- * lbm_get_deviations + lbm_lockin at step n of one solver and
- * lbm_set_deviations on another, this resumes a run from a checkpoint,
- * bit-exactly.  Waits for the stream. */
+ * sums (NULL = zeros).  The current state becomes that of step n; force
+ * history before n is no longer available.  Together with lbm_get_state +
+ * lbm_lockin at step n of one solver and lbm_set_state on another, this
+ * resumes a run from a checkpoint bit-exactly.  Waits for the stream. */
 int lbm_seek(lbm_solver* s, int64_t step, const double lockin_sums[6]);
 
 /* Wait for the stream, then free the solver.  NULL is a no-op. */
@@ -205,8 +229,11 @@ typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(void* hip_stream, lbm_batch** out);
 
 /* Add / remove a member (between steps).  LBM_EINVAL if the solver's stream,
- * lattice, storage or collision differs from the batch, or on a double add /
- * a remove of a non-member.  A member joins at its own current step. */
+ * lattice, storage or collision differs from the batch, if two members kept
+ * as populations differ in `tile`, or on a double add / a remove of a
+ * non-member.  A member joins at its own current step.  Members kept as
+ * populations and members kept as coefficients are advanced by one launch of
+ * each kernel per step. */
 int lbm_batch_add(lbm_batch* b, lbm_solver* s);
 int lbm_batch_remove(lbm_batch* b, lbm_solver* s);
 

@@ -13,6 +13,37 @@
 
 using namespace lbm;
 
+namespace lbm {
+
+// Workgroups of a launch are dealt to the 8 XCDs in turn (workgroup b runs on
+// XCD b % 8), and each XCD has its own L2.  Tiles of one lattice row share the
+// cache lines at their ends (the pulls are shifted by up to 3 cells), so the
+// rows ("super-rows" of `span` tiles, about one lattice row) are dealt to the
+// XCDs in turn: workgroups 8k..8k+7 take tile j of 8 consecutive rows.  All
+// XCDs then work on one compact band of rows at a time (good HBM page
+// locality) while every row stays within one L2.  Positions without a tile
+// are no-op items (tile -1), which also keeps the next solve aligned.
+void order_tiles(std::vector<WorkItem>* out, int32_t solve, int32_t ntiles, int32_t span) {
+  while (out->size() % 8) out->push_back(WorkItem{solve, -1});
+  span = std::max<int32_t>(1, span);
+  const int32_t nrows = (ntiles + span - 1) / span;
+  for (int32_t g = 0; g < nrows; g += 8)
+    for (int32_t k = 0; k < span; ++k)
+      for (int32_t i = 0; i < 8; ++i) {
+        const int32_t row = g + i, t = row * span + k;
+        out->push_back(WorkItem{solve, row < nrows && t < ntiles ? t : -1});
+      }
+}
+
+// Work-list length order_tiles produces for one solve starting aligned.
+int64_t ordered_length(int64_t ntiles, int64_t span) {
+  span = std::max<int64_t>(1, span);
+  const int64_t nrows = (ntiles + span - 1) / span;
+  return (nrows + 7) / 8 * 8 * span;
+}
+
+}  // namespace lbm
+
 namespace {
 
 template <class L>
@@ -43,6 +74,9 @@ int validate(const lbm_params* p, HostLattice* lat) {
   if (p->wall != LBM_WALL_BB) return LBM_EINVAL;
   if (p->far != LBM_FAR_WALL && p->far != LBM_FAR_EQ) return LBM_EINVAL;
   if (p->tile != 0 && p->tile != 1 && p->tile != 2 && p->tile != 4) return LBM_EINVAL;
+  if (p->representation > LBM_REPR_COEFFICIENTS) return LBM_EINVAL;
+  if (p->representation == LBM_REPR_COEFFICIENTS && p->collision != LBM_COLL_REGULARIZED)
+    return LBM_EINVAL;
   const int R = lat->R;
   if (p->nx < std::max(3, R) || p->ny < std::max(3, R)) return LBM_EINVAL;
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) return LBM_EINVAL;
@@ -88,8 +122,10 @@ bool is_link(const lbm_params* p, const HostLattice& L, int x, int y, int q) {
 // Tile -> partial slot table, and the rest-state part of the wall force
 // -sum_links 2 v_i w_i rho0 (exact link enumeration, long double).
 void plan_links(const lbm_params* p, const HostLattice& L, const Layout& lay,
-                std::vector<int32_t>* slot, int32_t* nslots, double fstatic[2]) {
+                std::vector<int32_t>* slot, int32_t* nslots, std::vector<int32_t>* mslot,
+                int32_t* mnslots, double fstatic[2]) {
   slot->assign(lay.ntiles, -1);
+  mslot->assign(std::max(lay.mntiles, 1), -1);
   long double sx = 0, sy = 0;
   int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
   if (p->geometry == LBM_GEOM_PLATE) {
@@ -109,12 +145,19 @@ void plan_links(const lbm_params* p, const HostLattice& L, const Layout& lay,
           sx -= L.vx[q] * m;
           sy -= L.vy[q] * m;
         }
-      if (any) (*slot)[((int64_t)y * p->nx + x) / lay.cells_per_tile] = 0;
+      if (any) {
+        (*slot)[((int64_t)y * p->nx + x) / lay.cells_per_tile] = 0;
+        if (lay.mom) (*mslot)[(y / kMomTileH) * lay.tiles_x + x / kMomTileW] = 0;
+      }
     }
   int32_t n = 0;
   for (auto& s : *slot)
     if (s >= 0) s = n++;
   *nslots = n;
+  n = 0;
+  for (auto& s : *mslot)
+    if (s >= 0) s = n++;
+  *mnslots = n;
   fstatic[0] = (double)sx;
   fstatic[1] = (double)sy;
 }
@@ -137,8 +180,20 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
     lay->ys = lay->pitch;
     lay->buf_elems = lay->qs * L.Q;
   }
+  lay->mom = p->representation == LBM_REPR_COEFFICIENTS ||
+             (p->representation == LBM_REPR_AUTO && p->collision == LBM_COLL_REGULARIZED &&
+              p->nx >= kMomTileW);
+  if (lay->mom) {
+    lay->tiles_x = (p->nx + kMomTileW - 1) / kMomTileW;
+    lay->mntiles = lay->tiles_x * ((p->ny + kMomTileH - 1) / kMomTileH);
+    lay->mpitch = (int64_t)align_up(p->nx, 64);
+    lay->mks = (int64_t)align_up((uint64_t)p->ny * lay->mpitch, 256) + 256;
+    lay->mbuf_bytes = 6 * (uint64_t)lay->mks * es;
+  }
   const int64_t ncells = (int64_t)p->nx * p->ny;
-  lay->cpt = p->tile ? (int32_t)p->tile : 1;
+  // the coefficient solver's population kernel (first step after a load)
+  // runs with one cell per thread
+  lay->cpt = lay->mom ? 1 : (p->tile ? (int32_t)p->tile : 1);
   lay->cells_per_tile = kBlock * lay->cpt;
   lay->ntiles = (int32_t)((ncells + lay->cells_per_tile - 1) / lay->cells_per_tile);
   lay->hist_cap = p->history_capacity ? p->history_capacity : p->max_steps;
@@ -150,18 +205,36 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   };
   lay->off_desc = take(sizeof(SolveDesc));
   lay->off_state = take(sizeof(SolveState));
-  lay->off_work = take(sizeof(WorkItem) * lay->ntiles);
+  // XCD-aware order pads each group of 8 rows to full length
+  lay->nwork = (int32_t)ordered_length(lay->ntiles, (p->nx + lay->cells_per_tile - 1) /
+                                                        lay->cells_per_tile);
+  lay->off_work = take(sizeof(WorkItem) * (uint64_t)lay->nwork);
+  if (lay->mom) {
+    lay->mnwork = (int32_t)ordered_length(lay->mntiles, lay->tiles_x);
+    lay->off_mwork = take(sizeof(WorkItem) * (uint64_t)lay->mnwork);
+    lay->off_mslot = take(sizeof(int32_t) * (uint64_t)lay->mntiles);
+  }
   lay->off_solves = take(sizeof(int32_t));
   lay->off_slot = take(sizeof(int32_t) * lay->ntiles);
   lay->off_part = 0;  // set after plan_links (needs nslots); reserve the worst case
-  lay->off_part = take(sizeof(double) * 2 * (uint64_t)lay->ntiles);
+  lay->off_part = take(sizeof(double) * 2 * (uint64_t)std::max(lay->ntiles, lay->mntiles));
   lay->off_drive = take(sizeof(Drive) * (uint64_t)p->max_steps);
   lay->off_hist = take(sizeof(double) * 2 * (uint64_t)lay->hist_cap);
   lay->buf_bytes = (uint64_t)lay->buf_elems * es;
   o = align_up(o, 4096);
   lay->off_buf[0] = take(lay->buf_bytes);
-  o = align_up(o, 4096);
-  lay->off_buf[1] = take(lay->buf_bytes);
+  if (lay->mom) {
+    // one population buffer (a loaded state, read by the next step) and two
+    // coefficient buffers
+    lay->off_buf[1] = lay->off_buf[0];
+    o = align_up(o, 4096);
+    lay->off_mbuf[0] = take(lay->mbuf_bytes);
+    o = align_up(o, 4096);
+    lay->off_mbuf[1] = take(lay->mbuf_bytes);
+  } else {
+    o = align_up(o, 4096);
+    lay->off_buf[1] = take(lay->buf_bytes);
+  }
   lay->total = o;
 }
 
@@ -174,16 +247,17 @@ int init_solver(lbm_solver* s) {
   const lbm_params* p = &s->p;
   const Layout& lay = s->lay;
   char* b = s->base;
-  std::vector<int32_t> slot;
+  std::vector<int32_t> slot, mslot;
   double fstatic[2];
-  int32_t nslots = 0;
-  plan_links(p, s->lat, lay, &slot, &nslots, fstatic);
+  int32_t nslots = 0, mnslots = 0;
+  plan_links(p, s->lat, lay, &slot, &nslots, &mslot, &mnslots, fstatic);
   s->lay.nslots = nslots;
+  s->lay.mnslots = mnslots;
 
   SolveDesc& d = s->desc;
   std::memset(&d, 0, sizeof(d));
-  d.buf[0] = b + lay.off_buf[0];
-  d.buf[1] = b + lay.off_buf[1];
+  s->bufs[0] = d.buf[0] = b + lay.off_buf[0];
+  s->bufs[1] = d.buf[1] = b + lay.off_buf[1];
   d.drive = reinterpret_cast<const Drive*>(b + lay.off_drive);
   d.hist = reinterpret_cast<double*>(b + lay.off_hist);
   d.state = reinterpret_cast<SolveState*>(b + lay.off_state);
@@ -214,12 +288,22 @@ int init_solver(lbm_solver* s) {
   d.ladd_scale = 2.0 * p->rho0 / s->lat.lw.theta;
   d.fstatic[0] = fstatic[0];
   d.fstatic[1] = fstatic[1];
+  if (lay.mom) {
+    d.mbuf[0] = b + lay.off_mbuf[0];
+    d.mbuf[1] = b + lay.off_mbuf[1];
+    d.mslot = reinterpret_cast<const int32_t*>(b + lay.off_mslot);
+    d.mks = lay.mks;
+    d.mys = lay.mpitch;
+    d.tiles_x = lay.tiles_x;
+    d.mnslots = mnslots;
+  }
 
   for (int k = 0; k < 8; ++k) s->klat.w[k] = s->lat.lw.w_orbit[k];
   s->klat.theta = s->lat.lw.theta;
 
-  std::vector<WorkItem> work(lay.ntiles);
-  for (int t = 0; t < lay.ntiles; ++t) work[t] = WorkItem{0, t};
+  std::vector<WorkItem> work, mwork;
+  order_tiles(&work, 0, lay.ntiles, (p->nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
+  if (lay.mom) order_tiles(&mwork, 0, lay.mntiles, lay.tiles_x);
   std::vector<Drive> drive((size_t)p->max_steps);
   for (int64_t n = 0; n < p->max_steps; ++n) {
     const double arg = p->omega * ((double)n + 0.5);
@@ -231,6 +315,7 @@ int init_solver(lbm_solver* s) {
   s->d_desc = reinterpret_cast<SolveDesc*>(b + lay.off_desc);
   s->d_work = reinterpret_cast<WorkItem*>(b + lay.off_work);
   s->d_solves = reinterpret_cast<int32_t*>(b + lay.off_solves);
+  s->d_mwork = lay.mom ? reinterpret_cast<WorkItem*>(b + lay.off_mwork) : nullptr;
 
   hipStream_t st = s->stream;
   int rc;
@@ -247,14 +332,26 @@ int init_solver(lbm_solver* s) {
   if ((rc = hip_rc(hipMemcpyAsync(b + lay.off_drive, drive.data(), sizeof(Drive) * drive.size(),
                                   hipMemcpyHostToDevice, st))))
     return rc;
+  if (lay.mom) {
+    if ((rc = hip_rc(hipMemcpyAsync(s->d_mwork, mwork.data(), sizeof(WorkItem) * mwork.size(),
+                                    hipMemcpyHostToDevice, st))))
+      return rc;
+    if ((rc = hip_rc(hipMemcpyAsync(b + lay.off_mslot, mslot.data(),
+                                    sizeof(int32_t) * lay.mntiles, hipMemcpyHostToDevice, st))))
+      return rc;
+    if ((rc = hip_rc(hipMemsetAsync(b + lay.off_mbuf[0], 0, lay.mbuf_bytes, st)))) return rc;
+    if ((rc = hip_rc(hipMemsetAsync(b + lay.off_mbuf[1], 0, lay.mbuf_bytes, st)))) return rc;
+  }
   // rest state (zero deviations), zero counters, sums and history
   if ((rc = hip_rc(hipMemsetAsync(b + lay.off_state, 0, sizeof(SolveState), st)))) return rc;
-  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_part, 0, sizeof(double) * 2 * lay.ntiles, st))))
+  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_part, 0,
+                                  sizeof(double) * 2 * std::max(lay.ntiles, lay.mntiles), st))))
     return rc;
   if ((rc = hip_rc(hipMemsetAsync(b + lay.off_hist, 0, sizeof(double) * 2 * lay.hist_cap, st))))
     return rc;
   if ((rc = hip_rc(hipMemsetAsync(b + lay.off_buf[0], 0, lay.buf_bytes, st)))) return rc;
-  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_buf[1], 0, lay.buf_bytes, st)))) return rc;
+  if (!lay.mom && (rc = hip_rc(hipMemsetAsync(b + lay.off_buf[1], 0, lay.buf_bytes, st))))
+    return rc;
   return hip_rc(hipStreamSynchronize(st));
 }
 
@@ -301,6 +398,36 @@ int create_common(const lbm_params* p, void* stream, void* dev_buf, uint64_t byt
   *out = s;
   return LBM_OK;
 }
+
+}  // namespace
+
+// One step of a single solver: the population kernel, the population kernel
+// writing coefficients (first step after populations were loaded into a
+// coefficient solver), or the coefficient kernel; then the finalize.
+int step_one(lbm_solver* s) {
+  const bool f64 = s->p.storage == LBM_STORE_F64;
+  const bool bgk = s->p.collision == LBM_COLL_BGK;
+  const int Q = (int)s->p.lattice;
+  int mode = 0;
+  hipError_t e;
+  if (!s->lay.mom) {
+    e = launch_step(Q, f64, bgk, s->lay.cpt, false, s->d_desc, s->d_work, s->lay.nwork, s->klat,
+                    s->stream);
+  } else if (s->pop_pending) {
+    e = launch_step(Q, f64, false, 1, true, s->d_desc, s->d_work, s->lay.nwork, s->klat,
+                    s->stream);
+    s->pop_pending = false;
+  } else {
+    e = launch_moment(Q, f64, s->d_desc, s->d_mwork, s->lay.mnwork, s->klat, s->stream);
+    mode = 1;
+  }
+  if (e != hipSuccess) return LBM_EHIP;
+  if (launch_finalize(s->d_desc, s->d_solves, 1, mode, s->stream) != hipSuccess) return LBM_EHIP;
+  ++s->steps;
+  return LBM_OK;
+}
+
+namespace {
 
 int sync_and_check(lbm_solver* s) {
   if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
@@ -368,14 +495,9 @@ int lbm_create_in(const lbm_params* p, void* hip_stream, void* dev_buf, uint64_t
 int lbm_step(lbm_solver* s, int64_t nsteps) {
   if (!s || nsteps < 0) return LBM_EINVAL;
   if (s->steps + nsteps > s->p.max_steps) return LBM_ERANGE;
-  const bool f64 = s->p.storage == LBM_STORE_F64;
-  const bool bgk = s->p.collision == LBM_COLL_BGK;
   for (int64_t k = 0; k < nsteps; ++k) {
-    if (launch_step((int)s->p.lattice, f64, bgk, s->lay.cpt, s->d_desc, s->d_work,
-                    s->lay.ntiles, s->klat, s->stream) != hipSuccess)
-      return LBM_EHIP;
-    if (launch_finalize(s->d_desc, s->d_solves, 1, s->stream) != hipSuccess) return LBM_EHIP;
-    ++s->steps;
+    int rc = step_one(s);
+    if (rc) return rc;
   }
   return LBM_OK;
 }
@@ -383,6 +505,12 @@ int lbm_step(lbm_solver* s, int64_t nsteps) {
 int lbm_synchronize(lbm_solver* s) {
   if (!s) return LBM_EINVAL;
   return sync_and_check(s);
+}
+
+int lbm_representation(const lbm_solver* s, int* repr) {
+  if (!s || !repr) return LBM_EINVAL;
+  *repr = s->lay.mom ? LBM_REPR_COEFFICIENTS : LBM_REPR_POPULATIONS;
+  return LBM_OK;
 }
 
 int lbm_steps_done(const lbm_solver* s, int64_t* n) {
@@ -470,32 +598,48 @@ int lbm_impedance(lbm_solver* s, double out[5]) {
 
 namespace {
 
-// Copy the current buffer out as FP64 [q][y][x]; with_rest adds w_i rho0.
+// Copy the current state out as FP64 [q][y][x] populations; with_rest adds
+// w_i rho0.  A coefficient state is expanded to populations
+// w_i (a0 + vx bx + vy by + vx^2 cxx + vx vy cxy + vy^2 cyy).
 int copy_out(lbm_solver* s, double* host, uint64_t n, bool with_rest) {
   if (!s || !host) return LBM_EINVAL;
   const lbm_params& p = s->p;
-  const int Q = s->lat.Q;
+  const HostLattice& L = s->lat;
+  const int Q = L.Q;
   if (n != (uint64_t)Q * p.ny * p.nx) return LBM_EINVAL;
   if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
   const bool f64 = p.storage == LBM_STORE_F64;
-  std::vector<char> stage(s->lay.buf_bytes);
-  if (hipMemcpy(stage.data(), s->desc.buf[s->steps & 1], s->lay.buf_bytes,
-                hipMemcpyDeviceToHost) != hipSuccess)
-    return LBM_EHIP;
+  const bool coeffs = s->lay.mom && !s->pop_pending;
+  const uint64_t bytes = coeffs ? s->lay.mbuf_bytes : s->lay.buf_bytes;
+  const void* src = coeffs ? s->desc.mbuf[s->steps & 1] : s->bufs[s->steps & 1];
+  std::vector<char> stage(bytes);
+  if (hipMemcpy(stage.data(), src, bytes, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EHIP;
+  auto at = [&](int64_t i) {
+    return f64 ? reinterpret_cast<const double*>(stage.data())[i]
+               : (double)reinterpret_cast<const float*>(stage.data())[i];
+  };
   for (int q = 0; q < Q; ++q) {
-    const double wr = with_rest ? s->lat.lw.w_orbit[s->lat.orbit[q]] * p.rho0 : 0.0;
+    const double w = L.lw.w_orbit[L.orbit[q]];
+    const double wr = with_rest ? w * p.rho0 : 0.0;
+    const double vx = L.vx[q], vy = L.vy[q];
     for (int y = 0; y < p.ny; ++y)
       for (int x = 0; x < p.nx; ++x) {
-        const int64_t src = q * s->lay.qs + y * s->lay.ys + x;
-        const double dv = f64 ? reinterpret_cast<const double*>(stage.data())[src]
-                              : (double)reinterpret_cast<const float*>(stage.data())[src];
+        double dv;
+        if (coeffs) {
+          const int64_t g = y * s->lay.mpitch + x, ks = s->lay.mks;
+          dv = w * (at(g) + vx * at(ks + g) + vy * at(2 * ks + g) + vx * vx * at(3 * ks + g) +
+                    vx * vy * at(4 * ks + g) + vy * vy * at(5 * ks + g));
+        } else {
+          dv = at(q * s->lay.qs + y * s->lay.ys + x);
+        }
         host[((size_t)q * p.ny + y) * p.nx + x] = in_body(&p, x, y) ? 0.0 : wr + dv;
       }
   }
   return LBM_OK;
 }
 
-// Copy FP64 [q][y][x] into the current buffer; with_rest subtracts w_i rho0.
+// Copy FP64 [q][y][x] into the current population buffer; with_rest
+// subtracts w_i rho0.  A coefficient solver reads it in its next step.
 int copy_in(lbm_solver* s, const double* host, uint64_t n, bool with_rest) {
   if (!s || !host) return LBM_EINVAL;
   const lbm_params& p = s->p;
@@ -514,10 +658,23 @@ int copy_in(lbm_solver* s, const double* host, uint64_t n, bool with_rest) {
         else reinterpret_cast<float*>(stage.data())[dst] = (float)dv;
       }
   }
-  if (hipMemcpy(s->desc.buf[s->steps & 1], stage.data(), s->lay.buf_bytes,
+  if (hipMemcpy(s->bufs[s->steps & 1], stage.data(), s->lay.buf_bytes,
                 hipMemcpyHostToDevice) != hipSuccess)
     return LBM_EHIP;
+  if (s->lay.mom) s->pop_pending = true;
   return LBM_OK;
+}
+
+// Raw state blob: header, then the current buffer.
+struct StateHeader {
+  uint32_t magic, lattice, storage, coeffs;
+  int32_t nx, ny;
+  uint64_t bytes;
+};
+constexpr uint32_t kStateMagic = 0x4c424d31;  // "LBM1"
+
+uint64_t state_payload(const lbm_solver* s) {
+  return (s->lay.mom && !s->pop_pending) ? s->lay.mbuf_bytes : s->lay.buf_bytes;
 }
 
 }  // namespace
@@ -541,10 +698,14 @@ int lbm_set_deviations(lbm_solver* s, const double* host, uint64_t n) {
 int lbm_seek(lbm_solver* s, int64_t step, const double lockin_sums[6]) {
   if (!s || step < 0 || step >= s->p.max_steps) return LBM_EINVAL;
   if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
-  if ((step & 1) != (s->steps & 1) &&
-      hipMemcpy(s->desc.buf[step & 1], s->desc.buf[s->steps & 1], s->lay.buf_bytes,
-                hipMemcpyDeviceToDevice) != hipSuccess)
-    return LBM_EHIP;
+  if ((step & 1) != (s->steps & 1)) {
+    // the current state moves to the buffer that step n reads
+    void* const* bufs = s->lay.mom && !s->pop_pending ? s->desc.mbuf : s->bufs;
+    if (bufs[step & 1] != bufs[s->steps & 1] &&
+        hipMemcpy(bufs[step & 1], bufs[s->steps & 1], state_payload(s),
+                  hipMemcpyDeviceToDevice) != hipSuccess)
+      return LBM_EHIP;
+  }
   SolveState st{};
   st.step = step;
   for (int k = 0; k < 6; ++k) st.lockin[k] = lockin_sums ? lockin_sums[k] : 0.0;
@@ -553,6 +714,46 @@ int lbm_seek(lbm_solver* s, int64_t step, const double lockin_sums[6]) {
   s->steps = step;
   s->hist_from = step;
   s->sticky_unstable = false;
+  return LBM_OK;
+}
+
+int lbm_state_size(const lbm_solver* s, uint64_t* bytes) {
+  if (!s || !bytes) return LBM_EINVAL;
+  *bytes = sizeof(StateHeader) + state_payload(s);
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_solver* s, void* host, uint64_t bytes) {
+  if (!s || !host) return LBM_EINVAL;
+  const uint64_t payload = state_payload(s);
+  if (bytes != sizeof(StateHeader) + payload) return LBM_EINVAL;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
+  const bool coeffs = s->lay.mom && !s->pop_pending;
+  StateHeader h{kStateMagic, s->p.lattice, s->p.storage, coeffs ? 1u : 0u, s->p.nx, s->p.ny,
+                payload};
+  std::memcpy(host, &h, sizeof(h));
+  const void* src = coeffs ? s->desc.mbuf[s->steps & 1] : s->bufs[s->steps & 1];
+  if (hipMemcpy(static_cast<char*>(host) + sizeof(h), src, payload, hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return LBM_EHIP;
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_solver* s, const void* host, uint64_t bytes) {
+  if (!s || !host || bytes < sizeof(StateHeader)) return LBM_EINVAL;
+  StateHeader h;
+  std::memcpy(&h, host, sizeof(h));
+  if (h.magic != kStateMagic || h.lattice != s->p.lattice || h.storage != s->p.storage ||
+      h.nx != s->p.nx || h.ny != s->p.ny || (h.coeffs && !s->lay.mom))
+    return LBM_EINVAL;
+  const uint64_t payload = h.coeffs ? s->lay.mbuf_bytes : s->lay.buf_bytes;
+  if (h.bytes != payload || bytes != sizeof(h) + payload) return LBM_EINVAL;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
+  void* dst = h.coeffs ? s->desc.mbuf[s->steps & 1] : s->bufs[s->steps & 1];
+  if (hipMemcpy(dst, static_cast<const char*>(host) + sizeof(h), payload,
+                hipMemcpyHostToDevice) != hipSuccess)
+    return LBM_EHIP;
+  if (s->lay.mom) s->pop_pending = !h.coeffs;
   return LBM_OK;
 }
 

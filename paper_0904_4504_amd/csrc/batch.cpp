@@ -20,12 +20,13 @@ struct lbm_batch {
   int Q = 0;
   uint32_t storage = 0, collision = 0;
   int cpt = 1;
+  bool have_pop = false;  // some member keeps populations (sets cpt)
   // current launch set (members that still have steps to run)
   std::vector<lbm_solver*> active;
   bool dirty = true;
-  int nwork = 0;
+  int nwork = 0, nmwork = 0;   // population-kernel and coefficient-kernel work items
   SolveDesc* d_descs = nullptr;
-  WorkItem* d_work = nullptr;
+  WorkItem* d_work = nullptr;   // population-kernel items, then coefficient-kernel items
   int32_t* d_solves = nullptr;
   size_t cap_descs = 0, cap_work = 0, cap_solves = 0;
   // graph of `graph_steps` steps for the current launch set
@@ -65,23 +66,28 @@ int grow(T** ptr, size_t* cap, size_t need) {
 }
 
 // Rebuild the device launch set from the members that have steps left.
-int refresh(lbm_batch* b) {
-  std::vector<lbm_solver*> act;
-  for (lbm_solver* s : b->members)
-    if (s->steps < s->p.max_steps) act.push_back(s);
+// Rebuild the device launch set from the given members.
+int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
   if (!b->dirty && act == b->active) return LBM_OK;
   drop_graph(b);
   b->active = act;
   b->dirty = false;
   std::vector<SolveDesc> descs;
-  std::vector<WorkItem> work;
+  std::vector<WorkItem> work, mwork;
   std::vector<int32_t> solves;
   for (size_t i = 0; i < act.size(); ++i) {
     descs.push_back(act[i]->desc);
     solves.push_back((int32_t)i);
-    for (int t = 0; t < act[i]->lay.ntiles; ++t) work.push_back(WorkItem{(int32_t)i, t});
+    const Layout& lay = act[i]->lay;
+    if (lay.mom)
+      order_tiles(&mwork, (int32_t)i, lay.mntiles, lay.tiles_x);
+    else
+      order_tiles(&work, (int32_t)i, lay.ntiles,
+                  (act[i]->p.nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
   }
   b->nwork = (int)work.size();
+  b->nmwork = (int)mwork.size();
+  work.insert(work.end(), mwork.begin(), mwork.end());
   if (act.empty()) return LBM_OK;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EHIP;
   int rc;
@@ -124,6 +130,15 @@ int collect_timing(lbm_batch* b) {
 int launch_one(lbm_batch* b) {
   const bool f64 = b->storage == LBM_STORE_F64, bgk = b->collision == LBM_COLL_BGK;
   const KernelLattice& lat = b->active[0]->klat;
+  auto step = [&]() {
+    hipError_t e = hipSuccess;
+    if (b->nwork > 0)
+      e = launch_step(b->Q, f64, bgk, b->cpt, false, b->d_descs, b->d_work, b->nwork, lat,
+                      b->stream);
+    if (e == hipSuccess && b->nmwork > 0)
+      e = launch_moment(b->Q, f64, b->d_descs, b->d_work + b->nwork, b->nmwork, lat, b->stream);
+    return e;
+  };
   if (b->timing) {
     if (b->ev_used + 2 > 4096) {
       int rc = collect_timing(b);
@@ -132,14 +147,13 @@ int launch_one(lbm_batch* b) {
     hipEvent_t e0 = next_event(b), e1 = next_event(b);
     if (!e0 || !e1) return LBM_EHIP;
     if (hipEventRecord(e0, b->stream) != hipSuccess) return LBM_EHIP;
-    if (launch_step(b->Q, f64, bgk, b->cpt, b->d_descs, b->d_work, b->nwork, lat, b->stream) != hipSuccess)
-      return LBM_EHIP;
+    if (step() != hipSuccess) return LBM_EHIP;
     if (hipEventRecord(e1, b->stream) != hipSuccess) return LBM_EHIP;
-  } else if (launch_step(b->Q, f64, bgk, b->cpt, b->d_descs, b->d_work, b->nwork, lat, b->stream) !=
-             hipSuccess) {
+  } else if (step() != hipSuccess) {
     return LBM_EHIP;
   }
-  if (launch_finalize(b->d_descs, b->d_solves, (int)b->active.size(), b->stream) != hipSuccess)
+  if (launch_finalize(b->d_descs, b->d_solves, (int)b->active.size(), 2, b->stream) !=
+      hipSuccess)
     return LBM_EHIP;
   return LBM_OK;
 }
@@ -195,10 +209,15 @@ int lbm_batch_add(lbm_batch* b, lbm_solver* s) {
     b->Q = (int)s->p.lattice;
     b->storage = s->p.storage;
     b->collision = s->p.collision;
-    b->cpt = s->lay.cpt;
   } else if ((int)s->p.lattice != b->Q || s->p.storage != b->storage ||
-             s->p.collision != b->collision || s->lay.cpt != b->cpt) {
+             s->p.collision != b->collision) {
     return LBM_EINVAL;
+  }
+  // members kept as populations share one population-kernel launch
+  if (!s->lay.mom) {
+    if (b->have_pop && s->lay.cpt != b->cpt) return LBM_EINVAL;
+    b->have_pop = true;
+    b->cpt = s->lay.cpt;
   }
   b->members.push_back(s);
   b->dirty = true;
@@ -214,6 +233,7 @@ int lbm_batch_remove(lbm_batch* b, lbm_solver* s) {
   b->dirty = true;
   if (b->members.empty()) {
     b->Q = 0;
+    b->have_pop = false;
   }
   return LBM_OK;
 }
@@ -231,13 +251,30 @@ int lbm_batch_size(const lbm_batch* b, int* members, int* active) {
 
 int lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
-  int64_t left = nsteps;
-  while (left > 0) {
-    int rc = refresh(b);
+  // steps each member still takes in this call
+  std::vector<int64_t> left(b->members.size());
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    lbm_solver* s = b->members[i];
+    left[i] = std::min(nsteps, s->p.max_steps - s->steps);
+    // a coefficient member whose state was just loaded as populations takes
+    // that step alone (population kernel writing coefficients)
+    if (s->pop_pending && left[i] > 0) {
+      int rc = step_one(s);
+      if (rc) return rc;
+      --left[i];
+    }
+  }
+  for (;;) {
+    std::vector<lbm_solver*> act;
+    int64_t chunk = 0;
+    for (size_t i = 0; i < b->members.size(); ++i)
+      if (left[i] > 0) {
+        act.push_back(b->members[i]);
+        chunk = chunk ? std::min(chunk, left[i]) : left[i];
+      }
+    if (act.empty()) break;
+    int rc = refresh(b, act);
     if (rc) return rc;
-    if (b->active.empty()) break;
-    int64_t chunk = left;
-    for (lbm_solver* s : b->active) chunk = std::min(chunk, s->p.max_steps - s->steps);
     int64_t k = 0;
     if (b->graphs_enabled && !b->timing && chunk >= b->graph_chunk) {
       if (!b->graph && !capture(b)) b->graphs_enabled = false;
@@ -246,8 +283,11 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps) {
     }
     for (; k < chunk; ++k)
       if ((rc = launch_one(b))) return rc;
-    for (lbm_solver* s : b->active) s->steps += chunk;
-    left -= chunk;
+    for (size_t i = 0; i < b->members.size(); ++i)
+      if (left[i] > 0) {
+        b->members[i]->steps += chunk;
+        left[i] -= chunk;
+      }
   }
   return LBM_OK;
 }

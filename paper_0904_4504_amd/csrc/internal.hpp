@@ -11,10 +11,12 @@
 
 namespace lbm {
 
-hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, const SolveDesc* descs,
+hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, bool outm, const SolveDesc* descs,
                        const WorkItem* work, int nwork, const KernelLattice& lat,
                        hipStream_t stream);
-hipError_t launch_finalize(const SolveDesc* descs, const int32_t* solves, int nsolves,
+hipError_t launch_moment(int Q, bool f64, const SolveDesc* descs, const WorkItem* work, int nwork,
+                         const KernelLattice& lat, hipStream_t stream);
+hipError_t launch_finalize(const SolveDesc* descs, const int32_t* solves, int nsolves, int mode,
                            hipStream_t stream);
 
 constexpr uint64_t kAlign = 256;
@@ -34,13 +36,28 @@ struct HostLattice {
 struct Layout {
   int64_t pitch = 0, qs = 0, ys = 0, buf_elems = 0;
   int32_t ntiles = 0, nslots = 0, cells_per_tile = kBlock, cpt = 1;
+  // coefficient representation (mom): 64 x 8 tiles, six coefficient planes
+  bool mom = false;
+  int32_t tiles_x = 0, mntiles = 0, mnslots = 0;
+  int64_t mpitch = 0, mks = 0;
+  uint64_t mbuf_bytes = 0, off_mslot = 0, off_mwork = 0, off_mbuf[2] = {0, 0};
+  int32_t nwork = 0, mnwork = 0;
   int64_t hist_cap = 0;
   uint64_t off_desc = 0, off_state = 0, off_work = 0, off_solves = 0, off_slot = 0,
            off_part = 0, off_drive = 0, off_hist = 0, off_buf[2] = {0, 0};
   uint64_t buf_bytes = 0, total = 0;
 };
 
+// Append the tiles of one solve to a launch work list in XCD-aware order
+// (rows of `span` tiles dealt to the 8 XCDs in turn).
+void order_tiles(std::vector<WorkItem>* out, int32_t solve, int32_t ntiles, int32_t span);
+
 }  // namespace lbm
+
+struct lbm_solver;
+// One step of a single solver (population, population-to-coefficient or
+// coefficient kernel, then the finalize); defined in api.cpp.
+int step_one(lbm_solver* s);
 
 struct lbm_solver {
   // solver state; host fields mirror the device counters after a sync
@@ -50,9 +67,12 @@ struct lbm_solver {
   lbm::KernelLattice klat{};
   hipStream_t stream = nullptr;
   char* base = nullptr;       // device allocation (owned or caller's)
+  void* bufs[2] = {nullptr, nullptr};  // population buffers; bufs[steps & 1] is current
   bool owned = false;
   int device = 0;
   int64_t steps = 0;          // steps enqueued
+  bool pop_pending = false;   // coefficient solver whose current state is populations
+  lbm::WorkItem* d_mwork = nullptr;
   lbm::SolveDesc desc{};      // host copy (device pointers)
   lbm::SolveDesc* d_desc = nullptr;
   lbm::WorkItem* d_work = nullptr;

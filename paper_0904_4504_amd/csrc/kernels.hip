@@ -32,24 +32,11 @@
 #include <type_traits>
 #include <utility>
 
+#include "device_util.hpp"
 #include "lattice.hpp"
 #include "solver.hpp"
 
 namespace lbm {
-
-template <int I, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Pull of population q into fluid cell (x, y) when the cell lies within R
 // cells of the domain edge or of the body: periodic wrap, bounce-back at the
@@ -115,8 +102,11 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
 }
 
 // Update of one cell: pull, moments, collision, store; adds the cell's wall
-// force contribution to (fx, fy).
-template <class L, typename S, bool BGK>
+// force contribution to (fx, fy).  OUTM stores the six H2 coefficients of the
+// post-collision state (a0, bx, by, cxx, cxy, cyy) to the coefficient planes
+// instead of the Q populations (regularized collision only; used for the first
+// step after populations were loaded into a solver kept in coefficients).
+template <class L, typename S, bool BGK, bool OUTM>
 __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restrict__ fin,
                                             S* __restrict__ fout, int64_t n, int c,
                                             const KernelLattice& lat, double& fx, double& fy) {
@@ -182,16 +172,28 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
     const S a0 = drho - (bxx + byy) * (S(0.5) * inv_th);
     const S bx = jx * inv_th, by = jy * inv_th;
     const S cxx = bxx * h2, cxy = bxy * (S(2) * h2), cyy = byy * h2;
-    if (fluid) static_for<0, Q>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      constexpr int vx = L::vx[q], vy = L::vy[q];
-      S p = a0;
-      if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
-      if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
-      if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
-      // output is not re-read in this step: stream it past the caches
-      __builtin_nontemporal_store((S)lat.w[L::orbit[q]] * p, &fout[q * qs + idx]);
-    });
+    if constexpr (OUTM) {
+      if (fluid) {
+        const int64_t g = y * d.mys + x;
+        fout[g] = a0;
+        fout[d.mks + g] = bx;
+        fout[2 * d.mks + g] = by;
+        fout[3 * d.mks + g] = cxx;
+        fout[4 * d.mks + g] = cxy;
+        fout[5 * d.mks + g] = cyy;
+      }
+    } else if (fluid) {
+      static_for<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int vx = L::vx[q], vy = L::vy[q];
+        S p = a0;
+        if constexpr (vx != 0) p += S(vx) * bx + S(vx * vx) * cxx;
+        if constexpr (vy != 0) p += S(vy) * by + S(vy * vy) * cyy;
+        if constexpr (vx * vy != 0) p += S(vx * vy) * cxy;
+        // output is not re-read in this step: stream it past the caches
+        __builtin_nontemporal_store((S)lat.w[L::orbit[q]] * p, &fout[q * qs + idx]);
+      });
+    }
   } else {
     // plain BGK: delta f^post = delta f + omega_r (delta f^eq - delta f)
     const S a0 = drho - (uxx + uyy) * (S(0.5) * inv_th);
@@ -212,55 +214,40 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
 
 // One workgroup of BS threads per tile of BS consecutive cells (row-major),
 // one cell per thread.
-template <class L, typename S, bool BGK, int BS>
+template <class L, typename S, bool BGK, int BS, bool OUTM>
 __global__ __launch_bounds__(BS) void step_kernel(const SolveDesc* __restrict__ descs,
                                                   const WorkItem* __restrict__ work,
                                                   KernelLattice lat) {
-  // Workgroups take their tiles in launch order (no XCD remapping): with
-  // row-interleaved storage the whole GPU then streams through one compact
-  // region of HBM at a time, which measured faster than giving each XCD its
-  // own band of rows.
+  // The host orders the work list so that workgroup b runs on XCD b % 8 with
+  // whole lattice rows per XCD (see order_tiles); padding items are no-ops.
   const WorkItem wi = work[blockIdx.x];
+  if (wi.tile < 0) return;
   const SolveDesc& d = descs[wi.solve];
   const int64_t n = d.state->step;
   const S* __restrict__ fin = static_cast<const S*>(d.buf[n & 1]);
-  S* __restrict__ fout = static_cast<S*>(d.buf[(n & 1) ^ 1]);
+  S* __restrict__ fout = static_cast<S*>(OUTM ? d.mbuf[(n & 1) ^ 1] : d.buf[(n & 1) ^ 1]);
   double fx = 0.0, fy = 0.0;
-  update_cell<L, S, BGK>(d, fin, fout, n, wi.tile * BS + (int)threadIdx.x, lat, fx, fy);
+  update_cell<L, S, BGK, OUTM>(d, fin, fout, n, wi.tile * BS + (int)threadIdx.x, lat, fx, fy);
 
   // per-tile force partial (fixed reduction order: lanes, then waves)
   const int slot = d.slot[wi.tile];
-  if (slot >= 0) {
-    __shared__ double red[2][BS / 64];
-    fx = wave_sum(fx);
-    fy = wave_sum(fy);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-      red[0][wave] = fx;
-      red[1][wave] = fy;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double sx = 0.0, sy = 0.0;
-#pragma unroll
-      for (int k = 0; k < BS / 64; ++k) {
-        sx += red[0][k];
-        sy += red[1][k];
-      }
-      d.partials[2 * slot] = sx;
-      d.partials[2 * slot + 1] = sy;
-    }
-  }
+  if (slot >= 0) block_force_partial<BS>(fx, fy, d.partials, slot);
 }
 
 // One workgroup per solve: sum the tile partials in slot order, add the
 // rest-state constant, append F_n to the history ring, accumulate the lock-in
 // sums when n lies in the window, and advance the step counter.
+// mode 0: the step ran the population kernel; 1: the coefficient kernel
+// (each has its own tile -> slot map); 2: per solve, the coefficient kernel
+// for solves that keep coefficients (batches).
 __global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __restrict__ descs,
-                                                          const int32_t* __restrict__ solves) {
+                                                          const int32_t* __restrict__ solves,
+                                                          int mode) {
   const SolveDesc& d = descs[solves[blockIdx.x]];
+  const bool coeffs = mode == 1 || (mode == 2 && d.mbuf[0] != nullptr);
+  const int nslots = coeffs ? d.mnslots : d.nslots;
   double fx = 0.0, fy = 0.0;
-  for (int s = threadIdx.x; s < d.nslots; s += kBlock) {
+  for (int s = threadIdx.x; s < nslots; s += kBlock) {
     fx += d.partials[2 * s];
     fy += d.partials[2 * s + 1];
   }
@@ -303,20 +290,30 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __res
 }
 
 template <class L, typename S, bool BGK>
-static hipError_t launch_step_t(int cpt, const SolveDesc* descs, const WorkItem* work, int nwork,
-                                const KernelLattice& lat, hipStream_t stream) {
+static hipError_t launch_step_t(int cpt, bool outm, const SolveDesc* descs, const WorkItem* work,
+                                int nwork, const KernelLattice& lat, hipStream_t stream) {
+  if (outm) {
+    if constexpr (BGK) {
+      return hipErrorInvalidValue;
+    } else {
+      if (cpt != 1) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((step_kernel<L, S, false, kBlock, true>), dim3(nwork), dim3(kBlock), 0,
+                         stream, descs, work, lat);
+      return hipGetLastError();
+    }
+  }
   switch (cpt) {
     case 1:
-      hipLaunchKernelGGL((step_kernel<L, S, BGK, kBlock>), dim3(nwork), dim3(kBlock), 0, stream,
-                         descs, work, lat);
+      hipLaunchKernelGGL((step_kernel<L, S, BGK, kBlock, false>), dim3(nwork), dim3(kBlock), 0,
+                         stream, descs, work, lat);
       break;
     case 2:
-      hipLaunchKernelGGL((step_kernel<L, S, BGK, 2 * kBlock>), dim3(nwork), dim3(2 * kBlock), 0,
-                         stream, descs, work, lat);
+      hipLaunchKernelGGL((step_kernel<L, S, BGK, 2 * kBlock, false>), dim3(nwork),
+                         dim3(2 * kBlock), 0, stream, descs, work, lat);
       break;
     case 4:
-      hipLaunchKernelGGL((step_kernel<L, S, BGK, 4 * kBlock>), dim3(nwork), dim3(4 * kBlock), 0,
-                         stream, descs, work, lat);
+      hipLaunchKernelGGL((step_kernel<L, S, BGK, 4 * kBlock, false>), dim3(nwork),
+                         dim3(4 * kBlock), 0, stream, descs, work, lat);
       break;
     default:
       return hipErrorInvalidValue;
@@ -324,26 +321,29 @@ static hipError_t launch_step_t(int cpt, const SolveDesc* descs, const WorkItem*
   return hipGetLastError();
 }
 
-hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, const SolveDesc* descs,
+hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, bool outm, const SolveDesc* descs,
                        const WorkItem* work, int nwork, const KernelLattice& lat,
                        hipStream_t stream) {
   if (nwork <= 0) return hipSuccess;
   if (Q == 9) {
-    if (f64) return bgk ? launch_step_t<D2Q9, double, true>(cpt, descs, work, nwork, lat, stream)
-                        : launch_step_t<D2Q9, double, false>(cpt, descs, work, nwork, lat, stream);
-    return bgk ? launch_step_t<D2Q9, float, true>(cpt, descs, work, nwork, lat, stream)
-               : launch_step_t<D2Q9, float, false>(cpt, descs, work, nwork, lat, stream);
+    if (f64)
+      return bgk ? launch_step_t<D2Q9, double, true>(cpt, outm, descs, work, nwork, lat, stream)
+                 : launch_step_t<D2Q9, double, false>(cpt, outm, descs, work, nwork, lat, stream);
+    return bgk ? launch_step_t<D2Q9, float, true>(cpt, outm, descs, work, nwork, lat, stream)
+               : launch_step_t<D2Q9, float, false>(cpt, outm, descs, work, nwork, lat, stream);
   }
-  if (f64) return bgk ? launch_step_t<D2Q37, double, true>(cpt, descs, work, nwork, lat, stream)
-                      : launch_step_t<D2Q37, double, false>(cpt, descs, work, nwork, lat, stream);
-  return bgk ? launch_step_t<D2Q37, float, true>(cpt, descs, work, nwork, lat, stream)
-             : launch_step_t<D2Q37, float, false>(cpt, descs, work, nwork, lat, stream);
+  if (f64)
+    return bgk ? launch_step_t<D2Q37, double, true>(cpt, outm, descs, work, nwork, lat, stream)
+               : launch_step_t<D2Q37, double, false>(cpt, outm, descs, work, nwork, lat, stream);
+  return bgk ? launch_step_t<D2Q37, float, true>(cpt, outm, descs, work, nwork, lat, stream)
+             : launch_step_t<D2Q37, float, false>(cpt, outm, descs, work, nwork, lat, stream);
 }
 
-hipError_t launch_finalize(const SolveDesc* descs, const int32_t* solves, int nsolves,
+hipError_t launch_finalize(const SolveDesc* descs, const int32_t* solves, int nsolves, int mode,
                            hipStream_t stream) {
   if (nsolves <= 0) return hipSuccess;
-  hipLaunchKernelGGL(finalize_kernel, dim3(nsolves), dim3(kBlock), 0, stream, descs, solves);
+  hipLaunchKernelGGL(finalize_kernel, dim3(nsolves), dim3(kBlock), 0, stream, descs, solves,
+                     mode);
   return hipGetLastError();
 }
 

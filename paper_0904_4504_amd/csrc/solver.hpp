@@ -7,6 +7,8 @@
 namespace lbm {
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
+constexpr int kMomTileW = 64;    // coefficient kernel: tile width (one wavefront per row)
+constexpr int kMomTileH = 8;     // coefficient kernel: tile height (two rows per thread)
 constexpr int kMaxSlots = 1 << 20;
 
 enum Geom : int32_t { GEOM_PLATE = 0, GEOM_BOX = 1, GEOM_PERIODIC = 2 };
@@ -36,6 +38,12 @@ struct SolveDesc {
   SolveState* state;
   double* partials;          // [nslots][2] per-tile force partial sums
   const int32_t* slot;       // [ntiles] tile -> partial slot, -1 if the tile has no wall link
+  void* mbuf[2];             // H2 coefficients (a0, bx, by, cxx, cxy, cyy) of the state, step
+                             // n reads mbuf[n & 1]; coefficient k of cell (x, y) at
+                             // k*mks + y*mys + x (null when the solver keeps populations)
+  const int32_t* mslot;      // [tiles_x*tiles_y] coefficient-kernel tile -> partial slot
+  int64_t mks, mys;
+  int32_t tiles_x, mnslots;
   int64_t qs;                // elements between the populations of one cell
   int64_t ys;                // elements between rows
   int64_t max_steps;

@@ -19,6 +19,7 @@ STORE_F64, STORE_F32_DEV = 0, 1
 COLL_REGULARIZED, COLL_BGK = 0, 1
 WALL_BB = 0
 GEOM_PLATE, GEOM_BOX, GEOM_PERIODIC = 0, 1, 2
+REPR_AUTO, REPR_POPULATIONS, REPR_COEFFICIENTS = 0, 1, 2
 FAR_WALL, FAR_EQ = 0, 1
 
 # every symbol include/lbm.h declares
@@ -28,7 +29,8 @@ EXPORTS = (
     "lbm_impedance", "lbm_get_populations", "lbm_set_populations", "lbm_destroy",
     "lbm_strerror", "lbm_seek", "lbm_get_deviations", "lbm_set_deviations", "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_size", "lbm_batch_step", "lbm_batch_synchronize", "lbm_batch_set_graphs",
-    "lbm_batch_timing", "lbm_batch_kernel_time", "lbm_batch_destroy",
+    "lbm_batch_timing", "lbm_batch_kernel_time", "lbm_batch_destroy", "lbm_state_size",
+    "lbm_get_state", "lbm_set_state", "lbm_representation",
 )
 
 
@@ -42,7 +44,8 @@ class Params(C.Structure):
     _fields_ = [
         ("abi_version", C.c_uint32), ("lattice", C.c_uint32), ("storage", C.c_uint32),
         ("collision", C.c_uint32), ("wall", C.c_uint32), ("geometry", C.c_uint32),
-        ("far", C.c_uint32), ("tile", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("far", C.c_uint32), ("tile", C.c_uint32), ("representation", C.c_uint32),
+        ("nx", C.c_int32), ("ny", C.c_int32),
         ("box_x0", C.c_int32), ("box_y0", C.c_int32), ("box_lx", C.c_int32),
         ("box_ly", C.c_int32), ("tau", C.c_double), ("omega", C.c_double),
         ("u0", C.c_double), ("rho0", C.c_double), ("max_steps", C.c_int64),
@@ -79,6 +82,10 @@ def lib():
         L.lbm_get_populations.argtypes = [vp, vp, C.c_uint64]
         L.lbm_set_populations.argtypes = [vp, vp, C.c_uint64]
         L.lbm_seek.argtypes = [vp, C.c_int64, vp]
+        L.lbm_state_size.argtypes = [vp, C.POINTER(C.c_uint64)]
+        L.lbm_get_state.argtypes = [vp, vp, C.c_uint64]
+        L.lbm_set_state.argtypes = [vp, vp, C.c_uint64]
+        L.lbm_representation.argtypes = [vp, C.POINTER(C.c_int)]
         L.lbm_get_deviations.argtypes = [vp, vp, C.c_uint64]
         L.lbm_set_deviations.argtypes = [vp, vp, C.c_uint64]
         L.lbm_destroy.argtypes = [vp]
@@ -124,10 +131,11 @@ def default_params():
     return p
 
 
-def params_from_solve(s, history_capacity=0, tile=0):
+def params_from_solve(s, history_capacity=0, tile=0, representation=REPR_AUTO):
     """lbm_params for an lbm_inputs.Solve."""
     p = default_params()
     p.tile = tile
+    p.representation = representation
     p.lattice = s.Q
     p.storage = STORE_F64 if s.storage == "f64" else STORE_F32_DEV
     p.collision = COLL_REGULARIZED if s.collision == "regularized" else COLL_BGK
@@ -232,6 +240,23 @@ class Solver:
         if d.shape != (self.Q, self.p.ny, self.p.nx):
             raise ValueError(f"deviations must have shape {(self.Q, self.p.ny, self.p.nx)}")
         _check(lib().lbm_set_deviations(self._h, d.ctypes.data, d.size), "lbm_set_deviations")
+
+    @property
+    def representation(self):
+        r = C.c_int()
+        _check(lib().lbm_representation(self._h, C.byref(r)), "lbm_representation")
+        return r.value
+
+    def get_state(self):
+        n = C.c_uint64()
+        _check(lib().lbm_state_size(self._h, C.byref(n)), "lbm_state_size")
+        buf = np.zeros(n.value, np.uint8)
+        _check(lib().lbm_get_state(self._h, buf.ctypes.data, n.value), "lbm_get_state")
+        return buf
+
+    def set_state(self, blob):
+        blob = np.ascontiguousarray(blob, np.uint8)
+        _check(lib().lbm_set_state(self._h, blob.ctypes.data, blob.size), "lbm_set_state")
 
     def seek(self, step, lockin_sums=None):
         sums = None if lockin_sums is None else np.ascontiguousarray(lockin_sums, np.float64)

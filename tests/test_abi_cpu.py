@@ -110,6 +110,8 @@ def _box(**kw):
     (_box, {"box_x0": 2}, B.EINVAL),
     (_box, {"box_lx": 2}, B.EINVAL),
     (_box, {"box_x0": 128 - 32 - 2}, B.EINVAL),
+    (_box, {"representation": 3}, B.EINVAL),
+    (_box, {"representation": B.REPR_COEFFICIENTS, "collision": B.COLL_BGK}, B.EINVAL),
 ])
 def test_required_bytes_validation(make, kw, code):
     with pytest.raises(P.LbmError) as e:
@@ -118,12 +120,17 @@ def test_required_bytes_validation(make, kw, code):
 
 
 def test_required_bytes_sizes():
+    cells = 128 * 128
+    p = _box(representation=B.REPR_POPULATIONS)
+    n = P.required_bytes(p)
+    assert 2 * 37 * cells * 4 <= n < 2 * 37 * cells * 4 * 1.2 + 1e6
+    # coefficients: one population buffer (a loaded state) + two of six coefficients
     p = _box()
     n = P.required_bytes(p)
-    cells = 128 * 128
-    assert n >= 2 * 37 * cells * 4
-    assert n < 2 * 37 * cells * 4 * 1.2 + 1e6
+    assert (37 + 12) * cells * 4 <= n < (37 + 12) * cells * 4 * 1.2 + 1e6
     p.storage = B.STORE_F64
+    assert P.required_bytes(p) >= (37 + 12) * cells * 8
+    p.collision = B.COLL_BGK
     assert P.required_bytes(p) >= 2 * 37 * cells * 8
     p.tau = float("inf")
     P.required_bytes(p)

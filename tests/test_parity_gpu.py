@@ -40,8 +40,8 @@ def _oracle_params(s, threads=0):
         box_x0=s.box[0], box_y0=s.box[1], box_lx=s.box[2], box_ly=s.box[3], nthreads=threads)
 
 
-def _gpu(P, s, f0=None, state=False, memory="torch", history_capacity=0):
-    p = P.params_from_solve(s, history_capacity)
+def _gpu(P, s, f0=None, state=False, memory="torch", history_capacity=0, repr_=0):
+    p = P.params_from_solve(s, history_capacity, representation=repr_)
     with P.Solver(p, memory=memory) as sv:
         if f0 is not None:
             sv.set_populations(f0)
@@ -86,15 +86,20 @@ def _small_solve(name, storage, nsteps=40):
                    storage=storage, collision=coll, name=name)
 
 
+@pytest.mark.parametrize("repr_", [1, 2], ids=["populations", "coefficients"])
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
 @pytest.mark.parametrize("name", list(SMALL))
-def test_small_parity(P, name, storage):
-    """Populations after 40 steps and every per-step force, element by element."""
+def test_small_parity(P, name, storage, repr_):
+    """Populations after 40 steps and every per-step force, element by element,
+    for both device representations (the first step reads the loaded
+    populations, later steps the H2 coefficients)."""
     s = _small_solve(name, storage)
-    print(f"case {name} {storage} {s.nx}x{s.ny}", flush=True)
+    if repr_ == 2 and s.collision != "regularized":
+        pytest.skip("coefficients hold only the regularized (H2) state")
+    print(f"case {name} {storage} repr {repr_} {s.nx}x{s.ny}", flush=True)
     v, w, th = P.lattice(s.Q)
-    f0 = _f0(s, w, seed=hash(name) % 1000, amp=1e-3)
-    fx, fy, z, f = _gpu(P, s, f0, state=True)
+    f0 = _f0(s, w, seed=sum(map(ord, name)) % 1000, amp=1e-3)
+    fx, fy, z, f = _gpu(P, s, f0, state=True, repr_=repr_)
     ox, oy, of = O.run(_oracle_params(s), s.nsteps, f0=f0, want_state=True, variant="ld")
     wo = O.lattice(s.Q, "ld")[1]
     dev_o = of - wo[:, None, None] * s.rho0
@@ -214,11 +219,13 @@ def test_deterministic_and_memory_owner_independent(P):
     assert np.array_equal(a[3], b[3])
 
 
+@pytest.mark.parametrize("name", ["q37_plate_wall_narrow", "q37_box"])
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
-def test_checkpoint_resume(P, storage):
-    """Run 40 steps straight, versus 20 steps -> checkpoint (populations +
-    lock-in sums) -> a new solver seeks to step 20 -> 20 more steps."""
-    s = _small_solve("q37_plate_wall_narrow", storage, nsteps=40)
+def test_checkpoint_resume(P, storage, name):
+    """Run 40 steps straight, versus 20 steps -> checkpoint (raw state +
+    lock-in sums) -> a new solver seeks to step 20 -> 20 more steps: bit-exact
+    in both representations."""
+    s = _small_solve(name, storage, nsteps=40)
     v, w, th = P.lattice(s.Q)
     f0 = _f0(s, w, 5, 1e-3)
     fx, fy, z, fend = _gpu(P, s, f0, state=True)
@@ -226,11 +233,11 @@ def test_checkpoint_resume(P, storage):
     with P.Solver(p) as a:
         a.set_populations(f0)
         a.step(20)
-        mid = a.get_deviations()
+        mid = a.get_state()
         sums, _ = a.lockin()
     with P.Solver(p) as b:
         b.seek(20, sums)
-        b.set_deviations(mid)
+        b.set_state(mid)
         b.step(20)
         fx2, _ = b.force_history(20, 20)
         z2 = b.impedance()
