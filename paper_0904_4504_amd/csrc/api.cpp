@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.hpp"
@@ -119,14 +120,74 @@ bool is_link(const lbm_params* p, const HostLattice& L, int x, int y, int q) {
   return false;
 }
 
-// Tile -> partial slot table, and the rest-state part of the wall force
-// -sum_links 2 v_i w_i rho0 (exact link enumeration, long double).
-void plan_links(const lbm_params* p, const HostLattice& L, const Layout& lay,
-                std::vector<int32_t>* slot, int32_t* nslots, std::vector<int32_t>* mslot,
-                int32_t* mnslots, double fstatic[2]) {
-  slot->assign(lay.ntiles, -1);
-  mslot->assign(std::max(lay.mntiles, 1), -1);
-  long double sx = 0, sy = 0;
+// True if the coefficient kernel must take its wall path at cell (x, y):
+// within R of the body (box) or of a bounce-back wall (plate).
+bool is_edge_cell(const lbm_params* p, int R, int x, int y) {
+  if (p->geometry == LBM_GEOM_BOX)
+    return x >= p->box_x0 - R && x < p->box_x0 + p->box_lx + R && y >= p->box_y0 - R &&
+           y < p->box_y0 + p->box_ly + R;
+  if (p->geometry == LBM_GEOM_PLATE) return y < R || (p->far == LBM_FAR_WALL && y >= p->ny - R);
+  return false;
+}
+
+// Coefficient-kernel tiles that contain a wall cell.
+std::vector<char> edge_tiles(const lbm_params* p, const HostLattice& L, const Layout& lay) {
+  std::vector<char> e(lay.mntiles, 0);
+  const int tiles_y = lay.mntiles / lay.tiles_x;
+  for (int ty = 0; ty < tiles_y; ++ty)
+    for (int tx = 0; tx < lay.tiles_x; ++tx) {
+      bool any = false;
+      for (int y = ty * kMomTileH; y < std::min(p->ny, (ty + 1) * kMomTileH) && !any; ++y)
+        for (int x = tx * kMomTileW; x < std::min(p->nx, (tx + 1) * kMomTileW) && !any; ++x)
+          any = is_edge_cell(p, L.R, x, y);
+      e[ty * lay.tiles_x + tx] = any;
+    }
+  return e;
+}
+
+// Mirror cell of the bounce-back link arriving at fluid cell (x, y) along q
+// (half-way walls; the same rules as the kernels).
+void mirror_of(const lbm_params* p, const HostLattice& L, int x, int y, int q, int* px, int* py) {
+  const int sx = x - L.vx[q], sy = y - L.vy[q];
+  if (p->geometry == LBM_GEOM_PLATE) {
+    *px = x;
+    *py = -1 - sy;
+    return;
+  }
+  const int x0 = p->box_x0, x1 = p->box_x0 + p->box_lx;
+  const int y0 = p->box_y0, y1 = p->box_y0 + p->box_ly;
+  *px = x < x0 ? 2 * x0 - 1 - sx : (x >= x1 ? 2 * x1 - 1 - sx : x);
+  *py = y < y0 ? 2 * y0 - 1 - sy : (y >= y1 ? 2 * y1 - 1 - sy : y);
+}
+
+// Momentum-exchange tables of the wall force.  Each bounce-back link (fluid
+// arrival x along v_i, mirror cell x_p) contributes
+//   -v_i (f_opp(x_p) + f_i^adv(x)) = -v_i (2 w_i rho0 + 2 df_opp(x_p) + 2 w_i rho0 (v_i.U_w)/theta)
+// with df the stored deviation.  The rest part and the moving-wall part are
+// geometry constants (fstatic, kladd times U_w), summed here in long double;
+// the deviation part becomes the link list (population state) or, per mirror
+// cell, two 6-vectors acting on the cell's H2 coefficients (coefficient state:
+// df_opp(x_p) = w_i (a0 - vx bx - vy by + vx^2 cxx + vx vy cxy + vy^2 cyy)).
+struct ForceTables {
+  std::vector<ForceLink> links;
+  std::vector<ForceCell> cells;
+  double fstatic[2] = {0, 0}, kladd[2] = {0, 0};
+};
+
+void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout& lay,
+                        ForceTables* t) {
+  long double sx = 0, sy = 0, kx = 0, ky = 0;
+  std::unordered_map<int64_t, size_t> index;  // mirror cell -> position in t->cells
+  auto cell_for = [&](int px, int py) -> ForceCell& {
+    const int64_t key = (int64_t)py * p->nx + px;
+    auto it = index.find(key);
+    if (it != index.end()) return t->cells[it->second];
+    ForceCell fc{};
+    fc.off = (int64_t)py * lay.mpitch + px;
+    index.emplace(key, t->cells.size());
+    t->cells.push_back(fc);
+    return t->cells.back();
+  };
   int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
   if (p->geometry == LBM_GEOM_PLATE) {
     x0 = 0; x1 = p->nx; y0 = 0; y1 = std::min(L.R, p->ny);
@@ -137,29 +198,34 @@ void plan_links(const lbm_params* p, const HostLattice& L, const Layout& lay,
   for (int y = y0; y < y1; ++y)
     for (int x = x0; x < x1; ++x) {
       if (in_body(p, x, y)) continue;
-      bool any = false;
-      for (int q = 0; q < L.Q; ++q)
-        if (is_link(p, L, x, y, q)) {
-          any = true;
-          const long double m = 2.0L * L.lw.w_orbit_ld[L.orbit[q]] * (long double)p->rho0;
-          sx -= L.vx[q] * m;
-          sy -= L.vy[q] * m;
+      for (int q = 0; q < L.Q; ++q) {
+        if (!is_link(p, L, x, y, q)) continue;
+        const long double w = L.lw.w_orbit_ld[L.orbit[q]];
+        const int vx = L.vx[q], vy = L.vy[q];
+        sx -= vx * 2.0L * w * p->rho0;
+        sy -= vy * 2.0L * w * p->rho0;
+        kx -= vx * 2.0L * w * p->rho0 * vx / L.lw.theta_ld;
+        ky -= vy * 2.0L * w * p->rho0 * vx / L.lw.theta_ld;
+        int px, py;
+        mirror_of(p, L, x, y, q, &px, &py);
+        t->links.push_back(ForceLink{L.opp[q] * lay.qs + py * lay.ys + px, -2.0 * vx, -2.0 * vy});
+        if (lay.mom) {
+          ForceCell& fc = cell_for(px, py);
+          // basis of the opposite direction -v at the mirror cell
+          const long double g[6] = {1, -(long double)vx, -(long double)vy,
+                                    (long double)vx * vx, (long double)vx * vy,
+                                    (long double)vy * vy};
+          for (int k = 0; k < 6; ++k) {
+            fc.wx[k] += (double)(-2.0L * vx * w * g[k]);
+            fc.wy[k] += (double)(-2.0L * vy * w * g[k]);
+          }
         }
-      if (any) {
-        (*slot)[((int64_t)y * p->nx + x) / lay.cells_per_tile] = 0;
-        if (lay.mom) (*mslot)[(y / kMomTileH) * lay.tiles_x + x / kMomTileW] = 0;
       }
     }
-  int32_t n = 0;
-  for (auto& s : *slot)
-    if (s >= 0) s = n++;
-  *nslots = n;
-  n = 0;
-  for (auto& s : *mslot)
-    if (s >= 0) s = n++;
-  *mnslots = n;
-  fstatic[0] = (double)sx;
-  fstatic[1] = (double)sy;
+  t->fstatic[0] = (double)sx;
+  t->fstatic[1] = (double)sy;
+  t->kladd[0] = (double)kx;
+  t->kladd[1] = (double)ky;
 }
 
 void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
@@ -212,12 +278,15 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   if (lay->mom) {
     lay->mnwork = (int32_t)ordered_length(lay->mntiles, lay->tiles_x);
     lay->off_mwork = take(sizeof(WorkItem) * (uint64_t)lay->mnwork);
-    lay->off_mslot = take(sizeof(int32_t) * (uint64_t)lay->mntiles);
+    lay->off_mework = take(sizeof(WorkItem) * (uint64_t)lay->mntiles);
   }
   lay->off_solves = take(sizeof(int32_t));
-  lay->off_slot = take(sizeof(int32_t) * lay->ntiles);
-  lay->off_part = 0;  // set after plan_links (needs nslots); reserve the worst case
-  lay->off_part = take(sizeof(double) * 2 * (uint64_t)std::max(lay->ntiles, lay->mntiles));
+  ForceTables ft;
+  build_force_tables(p, L, *lay, &ft);
+  lay->nlinks = (int32_t)ft.links.size();
+  lay->nfcells = (int32_t)ft.cells.size();
+  lay->off_links = take(sizeof(ForceLink) * ft.links.size());
+  lay->off_fcells = take(sizeof(ForceCell) * ft.cells.size());
   lay->off_drive = take(sizeof(Drive) * (uint64_t)p->max_steps);
   lay->off_hist = take(sizeof(double) * 2 * (uint64_t)lay->hist_cap);
   lay->buf_bytes = (uint64_t)lay->buf_elems * es;
@@ -247,12 +316,8 @@ int init_solver(lbm_solver* s) {
   const lbm_params* p = &s->p;
   const Layout& lay = s->lay;
   char* b = s->base;
-  std::vector<int32_t> slot, mslot;
-  double fstatic[2];
-  int32_t nslots = 0, mnslots = 0;
-  plan_links(p, s->lat, lay, &slot, &nslots, &mslot, &mnslots, fstatic);
-  s->lay.nslots = nslots;
-  s->lay.mnslots = mnslots;
+  ForceTables ft;
+  build_force_tables(p, s->lat, lay, &ft);
 
   SolveDesc& d = s->desc;
   std::memset(&d, 0, sizeof(d));
@@ -261,8 +326,10 @@ int init_solver(lbm_solver* s) {
   d.drive = reinterpret_cast<const Drive*>(b + lay.off_drive);
   d.hist = reinterpret_cast<double*>(b + lay.off_hist);
   d.state = reinterpret_cast<SolveState*>(b + lay.off_state);
-  d.partials = reinterpret_cast<double*>(b + lay.off_part);
-  d.slot = reinterpret_cast<const int32_t*>(b + lay.off_slot);
+  d.links = reinterpret_cast<const ForceLink*>(b + lay.off_links);
+  d.fcells = reinterpret_cast<const ForceCell*>(b + lay.off_fcells);
+  d.nlinks = lay.nlinks;
+  d.nfcells = lay.nfcells;
   d.qs = lay.qs;
   d.ys = lay.ys;
   d.max_steps = p->max_steps;
@@ -280,30 +347,38 @@ int init_solver(lbm_solver* s) {
     d.bx1 = p->box_x0 + p->box_lx;
     d.by1 = p->box_y0 + p->box_ly;
   }
-  d.ntiles = lay.ntiles;
-  d.nslots = nslots;
-  d.cells_per_tile = lay.cells_per_tile;
   d.inv_tau = std::isinf(p->tau) ? 0.0 : 1.0 / p->tau;
   d.rho0 = p->rho0;
   d.ladd_scale = 2.0 * p->rho0 / s->lat.lw.theta;
-  d.fstatic[0] = fstatic[0];
-  d.fstatic[1] = fstatic[1];
+  d.fstatic[0] = ft.fstatic[0];
+  d.fstatic[1] = ft.fstatic[1];
+  d.kladd[0] = ft.kladd[0];
+  d.kladd[1] = ft.kladd[1];
   if (lay.mom) {
     d.mbuf[0] = b + lay.off_mbuf[0];
     d.mbuf[1] = b + lay.off_mbuf[1];
-    d.mslot = reinterpret_cast<const int32_t*>(b + lay.off_mslot);
     d.mks = lay.mks;
     d.mys = lay.mpitch;
     d.tiles_x = lay.tiles_x;
-    d.mnslots = mnslots;
   }
 
   for (int k = 0; k < 8; ++k) s->klat.w[k] = s->lat.lw.w_orbit[k];
   s->klat.theta = s->lat.lw.theta;
 
-  std::vector<WorkItem> work, mwork;
+  std::vector<WorkItem> work, mwork, mework;
   order_tiles(&work, 0, lay.ntiles, (p->nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
-  if (lay.mom) order_tiles(&mwork, 0, lay.mntiles, lay.tiles_x);
+  if (lay.mom) {
+    // interior list in XCD-aware order with the wall tiles made no-ops; the
+    // wall tiles in their own list
+    order_tiles(&mwork, 0, lay.mntiles, lay.tiles_x);
+    const std::vector<char> edge = edge_tiles(p, s->lat, lay);
+    for (WorkItem& w : mwork)
+      if (w.tile >= 0 && edge[w.tile]) {
+        mework.push_back(w);
+        w.tile = -1;
+      }
+    s->lay.menwork = (int32_t)mework.size();
+  }
   std::vector<Drive> drive((size_t)p->max_steps);
   for (int64_t n = 0; n < p->max_steps; ++n) {
     const double arg = p->omega * ((double)n + 0.5);
@@ -316,6 +391,7 @@ int init_solver(lbm_solver* s) {
   s->d_work = reinterpret_cast<WorkItem*>(b + lay.off_work);
   s->d_solves = reinterpret_cast<int32_t*>(b + lay.off_solves);
   s->d_mwork = lay.mom ? reinterpret_cast<WorkItem*>(b + lay.off_mwork) : nullptr;
+  s->d_mework = lay.mom ? reinterpret_cast<WorkItem*>(b + lay.off_mework) : nullptr;
 
   hipStream_t st = s->stream;
   int rc;
@@ -326,8 +402,13 @@ int init_solver(lbm_solver* s) {
   if ((rc = hip_rc(hipMemcpyAsync(s->d_solves, &solve0, sizeof(solve0), hipMemcpyHostToDevice,
                                   st))))
     return rc;
-  if ((rc = hip_rc(hipMemcpyAsync(b + lay.off_slot, slot.data(), sizeof(int32_t) * slot.size(),
-                                  hipMemcpyHostToDevice, st))))
+  if (!ft.links.empty() &&
+      (rc = hip_rc(hipMemcpyAsync(b + lay.off_links, ft.links.data(),
+                                  sizeof(ForceLink) * ft.links.size(), hipMemcpyHostToDevice, st))))
+    return rc;
+  if (!ft.cells.empty() &&
+      (rc = hip_rc(hipMemcpyAsync(b + lay.off_fcells, ft.cells.data(),
+                                  sizeof(ForceCell) * ft.cells.size(), hipMemcpyHostToDevice, st))))
     return rc;
   if ((rc = hip_rc(hipMemcpyAsync(b + lay.off_drive, drive.data(), sizeof(Drive) * drive.size(),
                                   hipMemcpyHostToDevice, st))))
@@ -336,17 +417,17 @@ int init_solver(lbm_solver* s) {
     if ((rc = hip_rc(hipMemcpyAsync(s->d_mwork, mwork.data(), sizeof(WorkItem) * mwork.size(),
                                     hipMemcpyHostToDevice, st))))
       return rc;
-    if ((rc = hip_rc(hipMemcpyAsync(b + lay.off_mslot, mslot.data(),
-                                    sizeof(int32_t) * lay.mntiles, hipMemcpyHostToDevice, st))))
+    if (!mework.empty() &&
+        (rc = hip_rc(hipMemcpyAsync(s->d_mework, mework.data(), sizeof(WorkItem) * mework.size(),
+                                    hipMemcpyHostToDevice, st))))
       return rc;
+
     if ((rc = hip_rc(hipMemsetAsync(b + lay.off_mbuf[0], 0, lay.mbuf_bytes, st)))) return rc;
     if ((rc = hip_rc(hipMemsetAsync(b + lay.off_mbuf[1], 0, lay.mbuf_bytes, st)))) return rc;
   }
   // rest state (zero deviations), zero counters, sums and history
   if ((rc = hip_rc(hipMemsetAsync(b + lay.off_state, 0, sizeof(SolveState), st)))) return rc;
-  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_part, 0,
-                                  sizeof(double) * 2 * std::max(lay.ntiles, lay.mntiles), st))))
-    return rc;
+
   if ((rc = hip_rc(hipMemsetAsync(b + lay.off_hist, 0, sizeof(double) * 2 * lay.hist_cap, st))))
     return rc;
   if ((rc = hip_rc(hipMemsetAsync(b + lay.off_buf[0], 0, lay.buf_bytes, st)))) return rc;
@@ -401,6 +482,51 @@ int create_common(const lbm_params* p, void* stream, void* dev_buf, uint64_t byt
 
 }  // namespace
 
+namespace lbm {
+
+int SideStream::ensure() {
+  if (stream) return LBM_OK;
+  // default priority on purpose: the side stream must not outrank the main one
+  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return LBM_EHIP;
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
+    return LBM_EHIP;
+  return LBM_OK;
+}
+
+void SideStream::release() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  if (stream) (void)hipStreamDestroy(stream);
+  stream = nullptr;
+  fork = join = nullptr;
+}
+
+hipError_t launch_moment_pair(int Q, bool f64, const SolveDesc* descs, const WorkItem* interior,
+                              int ninterior, const WorkItem* edge, int nedge,
+                              const KernelLattice& lat, hipStream_t main, SideStream* side) {
+  hipError_t e;
+  if (nedge > 0) {
+    if (side->ensure() != LBM_OK) return hipErrorUnknown;
+    if ((e = hipEventRecord(side->fork, main)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess) return e;
+    if ((e = launch_moment(Q, f64, true, descs, edge, nedge, lat, side->stream)) != hipSuccess)
+      return e;
+    if ((e = hipEventRecord(side->join, side->stream)) != hipSuccess) return e;
+  }
+  if ((e = launch_moment(Q, f64, false, descs, interior, ninterior, lat, main)) != hipSuccess)
+    return e;
+  if (nedge > 0) return hipStreamWaitEvent(main, side->join, 0);
+  return hipSuccess;
+}
+
+}  // namespace lbm
+
+std::vector<char> solver_edge_tiles(const lbm_solver* s) {
+  return edge_tiles(&s->p, s->lat, s->lay);
+}
+
 // One step of a single solver: the population kernel, the population kernel
 // writing coefficients (first step after populations were loaded into a
 // coefficient solver), or the coefficient kernel; then the finalize.
@@ -418,11 +544,13 @@ int step_one(lbm_solver* s) {
                     s->stream);
     s->pop_pending = false;
   } else {
-    e = launch_moment(Q, f64, s->d_desc, s->d_mwork, s->lay.mnwork, s->klat, s->stream);
+    e = launch_moment_pair(Q, f64, s->d_desc, s->d_mwork, s->lay.mnwork, s->d_mework,
+                           s->lay.menwork, s->klat, s->stream, &s->side);
     mode = 1;
   }
   if (e != hipSuccess) return LBM_EHIP;
-  if (launch_finalize(s->d_desc, s->d_solves, 1, mode, s->stream) != hipSuccess) return LBM_EHIP;
+  if (launch_finalize(f64, s->d_desc, s->d_solves, 1, mode, s->stream) != hipSuccess)
+    return LBM_EHIP;
   ++s->steps;
   return LBM_OK;
 }
@@ -760,6 +888,7 @@ int lbm_set_state(lbm_solver* s, const void* host, uint64_t bytes) {
 int lbm_destroy(lbm_solver* s) {
   if (!s) return LBM_OK;
   int rc = hipStreamSynchronize(s->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+  s->side.release();
   if (s->owned && hipFree(s->base) != hipSuccess) rc = LBM_EHIP;
   delete s;
   return rc;

@@ -40,11 +40,12 @@ namespace lbm {
 
 // Pull of population q into fluid cell (x, y) when the cell lies within R
 // cells of the domain edge or of the body: periodic wrap, bounce-back at the
-// moving wall / body (with its force contribution), stationary far wall or
-// rest-equilibrium far field (delta f = 0).
+// moving wall / body (with the moving-wall term), stationary far wall or
+// rest-equilibrium far field (delta f = 0).  The wall force is computed from
+// the same input state by the finalize kernel.
 template <class L, typename S, int q>
 __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__ fin, int x,
-                                       int y, double ladd, double wq, double& fx, double& fy) {
+                                       int y, double ladd, double wq) {
   constexpr int vx = L::vx[q], vy = L::vy[q];
   constexpr int o = opposite<L>(q);
   const int nx = d.nx, ny = d.ny;
@@ -64,12 +65,7 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
       if (sy < 0) {
         // crossed the moving wall at y = -1/2: retrace in y, keep x
         const int py = -1 - sy;
-        const S fr = fin[o * qs + py * ys + x];
-        const double lad = wq * vx * ladd;
-        const double m = 2.0 * (double)fr + lad;
-        fx -= vx * m;
-        fy -= vy * m;
-        return fr + (S)lad;
+        return fin[o * qs + py * ys + x] + (S)(wq * vx * ladd);
       }
     }
     if constexpr (vy < 0) {
@@ -91,25 +87,19 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
     else if (x >= d.bx1) px = 2 * d.bx1 - 1 - sx;
     if (y < d.by0) py = 2 * d.by0 - 1 - sy;
     else if (y >= d.by1) py = 2 * d.by1 - 1 - sy;
-    const S fr = fin[o * qs + py * ys + px];
-    const double lad = wq * vx * ladd;
-    const double m = 2.0 * (double)fr + lad;
-    fx -= vx * m;
-    fy -= vy * m;
-    return fr + (S)lad;
+    return fin[o * qs + py * ys + px] + (S)(wq * vx * ladd);
   }
   return fin[q * qs + sy * ys + sx];
 }
 
-// Update of one cell: pull, moments, collision, store; adds the cell's wall
-// force contribution to (fx, fy).  OUTM stores the six H2 coefficients of the
+// Update of one cell: pull, moments, collision, store.  OUTM stores the six H2 coefficients of the
 // post-collision state (a0, bx, by, cxx, cxy, cyy) to the coefficient planes
 // instead of the Q populations (regularized collision only; used for the first
 // step after populations were loaded into a solver kept in coefficients).
 template <class L, typename S, bool BGK, bool OUTM>
 __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restrict__ fin,
                                             S* __restrict__ fout, int64_t n, int c,
-                                            const KernelLattice& lat, double& fx, double& fy) {
+                                            const KernelLattice& lat) {
   constexpr int Q = L::Q, R = L::R;
   const int nx = d.nx, ny = d.ny;
   const int64_t qs = d.qs, ys = d.ys;
@@ -134,7 +124,7 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
     const double ladd = d.ladd_scale * d.drive[n].u;
     static_for<0, Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      f[q] = pull_edge<L, S, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], fx, fy);
+      f[q] = pull_edge<L, S, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]]);
     });
   } else {
     static_for<0, Q>([&](auto qc) { f[decltype(qc)::value] = S(0); });
@@ -226,30 +216,45 @@ __global__ __launch_bounds__(BS) void step_kernel(const SolveDesc* __restrict__ 
   const int64_t n = d.state->step;
   const S* __restrict__ fin = static_cast<const S*>(d.buf[n & 1]);
   S* __restrict__ fout = static_cast<S*>(OUTM ? d.mbuf[(n & 1) ^ 1] : d.buf[(n & 1) ^ 1]);
-  double fx = 0.0, fy = 0.0;
-  update_cell<L, S, BGK, OUTM>(d, fin, fout, n, wi.tile * BS + (int)threadIdx.x, lat, fx, fy);
-
-  // per-tile force partial (fixed reduction order: lanes, then waves)
-  const int slot = d.slot[wi.tile];
-  if (slot >= 0) block_force_partial<BS>(fx, fy, d.partials, slot);
+  update_cell<L, S, BGK, OUTM>(d, fin, fout, n, wi.tile * BS + (int)threadIdx.x, lat);
 }
 
-// One workgroup per solve: sum the tile partials in slot order, add the
-// rest-state constant, append F_n to the history ring, accumulate the lock-in
-// sums when n lies in the window, and advance the step counter.
-// mode 0: the step ran the population kernel; 1: the coefficient kernel
-// (each has its own tile -> slot map); 2: per solve, the coefficient kernel
-// for solves that keep coefficients (batches).
-__global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __restrict__ descs,
-                                                          const int32_t* __restrict__ solves,
-                                                          int mode) {
-  const SolveDesc& d = descs[solves[blockIdx.x]];
+// One workgroup per solve.  Wall force of step n by momentum exchange (Sec.
+// 2 force F_f; eq. BB): every bounce-back link carries -v_i (f_opp(x_p) +
+// f_i^adv(x)) = -v_i (2 f_opp(x_p) + 2 w_i rho0 (v_i.U_w)/theta) (+ the rest
+// state), so F_n = F_static + K_ladd U_w(n) + sum over links of the reflected
+// populations of step n's input state, read here from the step's input buffer
+// (untouched by the step) and summed in a fixed order in FP64.  Then append
+// F_n to the history ring, accumulate the lock-in sums when n lies in the
+// window, and advance the step counter.
+// mode 0: the step read populations; 1: coefficients; 2: per solve,
+// coefficients if the solve keeps them (batches).
+template <typename S>
+__device__ void finalize_solve(const SolveDesc& d, int mode) {
+  SolveState* st = d.state;
+  const int64_t n = st->step;
   const bool coeffs = mode == 1 || (mode == 2 && d.mbuf[0] != nullptr);
-  const int nslots = coeffs ? d.mnslots : d.nslots;
   double fx = 0.0, fy = 0.0;
-  for (int s = threadIdx.x; s < nslots; s += kBlock) {
-    fx += d.partials[2 * s];
-    fy += d.partials[2 * s + 1];
+  if (coeffs) {
+    const S* __restrict__ c = static_cast<const S*>(d.mbuf[n & 1]);
+    const int64_t ks = d.mks;
+    for (int i = threadIdx.x; i < d.nfcells; i += kBlock) {
+      const ForceCell& fc = d.fcells[i];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const double v = (double)c[k * ks + fc.off];
+        fx += fc.wx[k] * v;
+        fy += fc.wy[k] * v;
+      }
+    }
+  } else {
+    const S* __restrict__ f = static_cast<const S*>(d.buf[n & 1]);
+    for (int i = threadIdx.x; i < d.nlinks; i += kBlock) {
+      const ForceLink& l = d.links[i];
+      const double v = (double)f[l.off];
+      fx += l.wx * v;
+      fy += l.wy * v;
+    }
   }
   __shared__ double red[2][kBlock / 64];
   fx = wave_sum(fx);
@@ -261,23 +266,19 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __res
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    fx = d.fstatic[0];
-    fy = d.fstatic[1];
+    const Drive dr = d.drive[n];
     double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int k = 0; k < kBlock / 64; ++k) {
       sx += red[0][k];
       sy += red[1][k];
     }
-    fx += sx;
-    fy += sy;
-    SolveState* st = d.state;
-    const int64_t n = st->step;
+    fx = d.fstatic[0] + d.kladd[0] * dr.u + sx;
+    fy = d.fstatic[1] + d.kladd[1] * dr.u + sy;
     const int64_t h = n % d.hist_cap;
     d.hist[2 * h] = fx;
     d.hist[2 * h + 1] = fy;
     if (n >= d.lockin_first && n < d.lockin_first + d.lockin_count) {
-      const Drive dr = d.drive[n];
       st->lockin[0] += fx * dr.s;
       st->lockin[1] += fx * dr.c;
       st->lockin[2] += fx;
@@ -287,6 +288,13 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __res
     }
     st->step = n + 1;
   }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __restrict__ descs,
+                                                          const int32_t* __restrict__ solves,
+                                                          int mode) {
+  finalize_solve<S>(descs[solves[blockIdx.x]], mode);
 }
 
 template <class L, typename S, bool BGK>
@@ -339,11 +347,15 @@ hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, bool outm, const Solv
              : launch_step_t<D2Q37, float, false>(cpt, outm, descs, work, nwork, lat, stream);
 }
 
-hipError_t launch_finalize(const SolveDesc* descs, const int32_t* solves, int nsolves, int mode,
-                           hipStream_t stream) {
+hipError_t launch_finalize(bool f64, const SolveDesc* descs, const int32_t* solves, int nsolves,
+                           int mode, hipStream_t stream) {
   if (nsolves <= 0) return hipSuccess;
-  hipLaunchKernelGGL(finalize_kernel, dim3(nsolves), dim3(kBlock), 0, stream, descs, solves,
-                     mode);
+  if (f64)
+    hipLaunchKernelGGL(finalize_kernel<double>, dim3(nsolves), dim3(kBlock), 0, stream, descs,
+                       solves, mode);
+  else
+    hipLaunchKernelGGL(finalize_kernel<float>, dim3(nsolves), dim3(kBlock), 0, stream, descs,
+                       solves, mode);
   return hipGetLastError();
 }
 

@@ -14,8 +14,8 @@
 // Walls: cells within R of a bounce-back wall or of the body rebuild each
 // crossing population from the mirror cell's coefficients in the opposite
 // direction plus the moving-wall term 2 w_i rho0 (v_i.U_w)/theta (Sec. 4,
-// eq. BB; the same half-way mirror rules as the population kernel) and add
-// its momentum exchange to the FP64 force.  Outside the domain the staged
+// eq. BB; the same half-way mirror rules as the population kernel); the
+// finalize kernel sums the momentum exchange from the same input state.  Outside the domain the staged
 // coefficients are periodic images (x for plates, x and y for periodic
 // domains) or zero, i.e. the rest-equilibrium far field.
 #include <hip/hip_runtime.h>
@@ -50,7 +50,9 @@ __device__ __forceinline__ S poly(const V4& a, const V2& b) {
   return p;
 }
 
-template <class L, typename S>
+// EDGE = false: tiles in which no cell has a bounce-back link (the host
+// classifies tiles); no wall code, no force.  EDGE = true: the other tiles.
+template <class L, typename S, bool EDGE>
 __global__ __launch_bounds__(kBlock) void moment_kernel(const SolveDesc* __restrict__ descs,
                                                         const WorkItem* __restrict__ work,
                                                         KernelLattice lat) {
@@ -103,23 +105,22 @@ __global__ __launch_bounds__(kBlock) void moment_kernel(const SolveDesc* __restr
   const S h2 = (S)(0.5 / (lat.theta * lat.theta));
   const S om = (S)d.inv_tau;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double fx = 0.0, fy = 0.0;
   const bool is_box = d.geom == GEOM_BOX;
 
-#pragma unroll 1
+#pragma unroll
   for (int r = 0; r < ROWS; ++r) {
     const int ly = wave * ROWS + r;
     const int x = x0 + lane, y = y0 + ly;
     if (x >= nx || y >= ny) continue;
-    if (is_box && x >= d.bx0 && x < d.bx1 && y >= d.by0 && y < d.by1) continue;
     const int ci = (ly + R) * HW + lane + R;
-    bool edge;
-    if (is_box)
-      edge = x >= d.bx0 - R && x < d.bx1 + R && y >= d.by0 - R && y < d.by1 + R;
-    else if (d.geom == GEOM_PLATE)
-      edge = y < R || (d.far == FAR_WALL && y >= ny - R);
-    else
-      edge = false;
+    bool edge = false;
+    if constexpr (EDGE) {
+      if (is_box && x >= d.bx0 && x < d.bx1 && y >= d.by0 && y < d.by1) continue;
+      if (is_box)
+        edge = x >= d.bx0 - R && x < d.bx1 + R && y >= d.by0 - R && y < d.by1 + R;
+      else if (d.geom == GEOM_PLATE)
+        edge = y < R || (d.far == FAR_WALL && y >= ny - R);
+    }
 
     S drho = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
     auto accumulate = [&](auto qc, S f) {
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void moment_kernel(const SolveDesc* __restr
         const S f = (S)lat.w[L::orbit[q]] * poly<vx, vy, 1, V4, V2, S>(A[ci - off], B[ci - off]);
         accumulate(qc, f);
       });
-    } else {
+    } else if constexpr (EDGE) {
       const double ladd = d.ladd_scale * d.drive[n].u;
       static_for<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void moment_kernel(const SolveDesc* __restr
         const double wq = lat.w[L::orbit[q]];
         const int sx = x - vx, sy = y - vy;
         // mirror cell of a bounce-back link (-1: not a link); `moving` adds
-        // the wall term and the force
+        // the wall term (the force is summed by the finalize kernel)
         int px = -1, py = -1;
         bool moving = false;
         if (is_box) {
@@ -177,15 +178,7 @@ __global__ __launch_bounds__(kBlock) void moment_kernel(const SolveDesc* __restr
         if (py >= 0) {
           const int cm = (py - y0 + R) * HW + (px - x0 + R);
           const S fr = (S)wq * poly<vx, vy, -1, V4, V2, S>(A[cm], B[cm]);
-          if (moving) {
-            const double lad = wq * vx * ladd;
-            const double m = 2.0 * (double)fr + lad;
-            fx -= vx * m;
-            fy -= vy * m;
-            f = fr + (S)lad;
-          } else {
-            f = fr;
-          }
+          f = moving ? fr + (S)(wq * vx * ladd) : fr;
         } else {
           f = (S)wq * poly<vx, vy, 1, V4, V2, S>(A[ci - off], B[ci - off]);
         }
@@ -211,29 +204,28 @@ __global__ __launch_bounds__(kBlock) void moment_kernel(const SolveDesc* __restr
     __builtin_nontemporal_store(byy * h2, &mout[5 * ks + g]);
   }
 
-  const int slot = d.mslot[wi.tile];
-  if (slot >= 0) block_force_partial<kBlock>(fx, fy, d.partials, slot);
 }
 
-hipError_t launch_moment(int Q, bool f64, const SolveDesc* descs, const WorkItem* work, int nwork,
-                         const KernelLattice& lat, hipStream_t stream) {
-  if (nwork <= 0) return hipSuccess;
-  if (Q == 9) {
-    if (f64)
-      hipLaunchKernelGGL((moment_kernel<D2Q9, double>), dim3(nwork), dim3(kBlock), 0, stream,
-                         descs, work, lat);
-    else
-      hipLaunchKernelGGL((moment_kernel<D2Q9, float>), dim3(nwork), dim3(kBlock), 0, stream,
-                         descs, work, lat);
-  } else {
-    if (f64)
-      hipLaunchKernelGGL((moment_kernel<D2Q37, double>), dim3(nwork), dim3(kBlock), 0, stream,
-                         descs, work, lat);
-    else
-      hipLaunchKernelGGL((moment_kernel<D2Q37, float>), dim3(nwork), dim3(kBlock), 0, stream,
-                         descs, work, lat);
-  }
+template <class L, typename S>
+static hipError_t launch_moment_t(bool edge, const SolveDesc* descs, const WorkItem* work,
+                                  int nwork, const KernelLattice& lat, hipStream_t stream) {
+  if (edge)
+    hipLaunchKernelGGL((moment_kernel<L, S, true>), dim3(nwork), dim3(kBlock), 0, stream, descs,
+                       work, lat);
+  else
+    hipLaunchKernelGGL((moment_kernel<L, S, false>), dim3(nwork), dim3(kBlock), 0, stream, descs,
+                       work, lat);
   return hipGetLastError();
+}
+
+hipError_t launch_moment(int Q, bool f64, bool edge, const SolveDesc* descs, const WorkItem* work,
+                         int nwork, const KernelLattice& lat, hipStream_t stream) {
+  if (nwork <= 0) return hipSuccess;
+  if (Q == 9)
+    return f64 ? launch_moment_t<D2Q9, double>(edge, descs, work, nwork, lat, stream)
+               : launch_moment_t<D2Q9, float>(edge, descs, work, nwork, lat, stream);
+  return f64 ? launch_moment_t<D2Q37, double>(edge, descs, work, nwork, lat, stream)
+             : launch_moment_t<D2Q37, float>(edge, descs, work, nwork, lat, stream);
 }
 
 }  // namespace lbm

@@ -8,7 +8,7 @@ namespace lbm {
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
 constexpr int kMomTileW = 64;    // coefficient kernel: tile width (one wavefront per row)
-constexpr int kMomTileH = 8;     // coefficient kernel: tile height (two rows per thread)
+constexpr int kMomTileH = 4;     // coefficient kernel: tile height (one row per wavefront)
 constexpr int kMaxSlots = 1 << 20;
 
 enum Geom : int32_t { GEOM_PLATE = 0, GEOM_BOX = 1, GEOM_PERIODIC = 2 };
@@ -29,6 +29,20 @@ struct SolveState {
   double lockin[6];    // x: sum F sin, sum F cos, sum F; then the same for y
 };
 
+// Momentum exchange of the wall force, precomputed per solve on the host.
+// Population state: F += (wx, wy) * buf[off] for every bounce-back link
+// (off = the reflected population at the mirror cell).
+struct ForceLink {
+  int64_t off;
+  double wx, wy;
+};
+// Coefficient state: F += (wx . c, wy . c) per mirror cell, c_k = mbuf[k*mks + off]
+// (the cell's links folded into two 6-vectors).
+struct ForceCell {
+  int64_t off;
+  double wx[6], wy[6];
+};
+
 // Everything a kernel needs to advance one solve; lives in device memory.
 // Pointers are device addresses.
 struct SolveDesc {
@@ -36,14 +50,13 @@ struct SolveDesc {
   const Drive* drive;        // [max_steps]
   double* hist;              // force ring [hist_cap][2]
   SolveState* state;
-  double* partials;          // [nslots][2] per-tile force partial sums
-  const int32_t* slot;       // [ntiles] tile -> partial slot, -1 if the tile has no wall link
+  const ForceLink* links;    // [nlinks]
+  const ForceCell* fcells;   // [nfcells] (coefficient state only)
   void* mbuf[2];             // H2 coefficients (a0, bx, by, cxx, cxy, cyy) of the state, step
                              // n reads mbuf[n & 1]; coefficient k of cell (x, y) at
                              // k*mks + y*mys + x (null when the solver keeps populations)
-  const int32_t* mslot;      // [tiles_x*tiles_y] coefficient-kernel tile -> partial slot
   int64_t mks, mys;
-  int32_t tiles_x, mnslots;
+  int32_t tiles_x, pad2;
   int64_t qs;                // elements between the populations of one cell
   int64_t ys;                // elements between rows
   int64_t max_steps;
@@ -52,13 +65,12 @@ struct SolveDesc {
   int32_t nx, ny, ncells, pad1;    // ncells = nx * ny (row-major cell index y*nx + x)
   int32_t geom, far;
   int32_t bx0, by0, bx1, by1;      // solid cells [bx0,bx1) x [by0,by1) (box only)
-  int32_t ntiles, nslots;
-  int32_t cells_per_tile;
-  int32_t pad0;
+  int32_t nlinks, nfcells;
   double inv_tau;                  // 1/tau (0 for tau = +inf)
   double rho0;
   double ladd_scale;               // 2 rho0 / theta: moving-wall term per unit (w_i v_i.U)
   double fstatic[2];               // rest-state part of the wall force (geometry constant)
+  double kladd[2];                 // force of the moving-wall terms per unit U_w
 };
 
 // One entry of the launch work list: a tile of one solve.
