@@ -35,7 +35,7 @@ CSRC = os.path.join(ROOT, "paper_0904_4504_amd", "csrc")
 KERNELS = {
     1: ("lbm::step_kernel<D2Q37, float, false, 256, false>", "kernels.hip",
         "step_kernel_beam_box_counters.json"),
-    2: ("lbm::moment_kernel<D2Q37, float>", "moments.hip", "moment_kernel_beam_box_counters.json"),
+    2: ("lbm::coef_kernel<D2Q37, float, {rb}>", "coef.hip", "coef_kernel_beam_box_counters.json"),
 }
 
 
@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--representation", type=int, default=0,
                     help="0 automatic, 1 populations, 2 H2 coefficients")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="kernel tile (cells per thread of the population or the coefficient "
+                         "kernel); 0 = library default")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solves of a sweep are independent and would "
@@ -125,7 +128,8 @@ def main():
     solves, desc = workload(a.workload, a.steps, a.warmup)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        solvers = [P.Solver(P.params_from_solve(s, representation=a.representation),
+        solvers = [P.Solver(P.params_from_solve(s, representation=a.representation,
+                                                tile=a.tile),
                             stream=stream) for s in solves]
         repr_ = solvers[0].representation
         batch = P.Batch(stream)
@@ -183,7 +187,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": KERNELS[repr_][0],
+            # tile 0 selects K = 2 cells per thread for coefficient solvers
+            # (include/lbm.h)
+            "kernel": KERNELS[repr_][0].format(rb=a.tile or 2),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -101,12 +101,17 @@ typedef struct lbm_params {
   uint32_t wall;         /* LBM_WALL_BB */
   uint32_t geometry;     /* LBM_GEOM_* */
   uint32_t far;          /* LBM_FAR_* */
-  uint32_t tile;         /* tile of the fused kernel: 0 (= 1), 1, 2 or 4; one workgroup of
+  uint32_t tile;         /* kernel tile.  Populations: 0 (= 1), 1, 2 or 4; one workgroup of
                             256*tile threads updates 256*tile consecutive cells, one per
-                            thread.  Batch members must agree. */
+                            thread.  Coefficients: 0 (= 2), 1, 2 or 3 = K; one workgroup
+                            of 256 threads updates a tile of 64 columns x 4K rows, K
+                            cells per thread.  Batch members kept in the same
+                            representation must agree. */
   uint32_t representation; /* device state: 0 = automatic, 1 = the Q populations, 2 = the six
                             H2 coefficients of the regularized post-collision state
-                            (regularized collision only; automatic picks 2 when nx >= 64) */
+                            (regularized collision only; automatic picks 2 when nx >= 64
+                            and one coefficient plane, ny x nx rounded up to 64, stays
+                            under 2 GiB) */
   int32_t nx, ny;        /* domain in cells; nx >= 3 and ny >= 3 */
   int32_t box_x0, box_y0, box_lx, box_ly; /* BOX only; sides and margins >= longest link */
   double tau;            /* relaxation time of the update, > 1/2; +inf allowed (BGK: free streaming) */
@@ -230,7 +235,7 @@ int lbm_batch_create(void* hip_stream, lbm_batch** out);
 
 /* Add / remove a member (between steps).  LBM_EINVAL if the solver's stream,
  * lattice, storage or collision differs from the batch, if two members kept
- * as populations differ in `tile`, or on a double add / a remove of a
+ * in the same representation differ in `tile`, or on a double add / a remove of a
  * non-member.  A member joins at its own current step.  Members kept as
  * populations and members kept as coefficients are advanced by one launch of
  * each kernel per step. */

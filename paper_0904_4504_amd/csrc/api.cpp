@@ -66,6 +66,19 @@ bool host_lattice(int Q, HostLattice* h) {
   return lattice_weights(Q, &h->lw);
 }
 
+// One coefficient plane must stay addressable with 32-bit byte offsets.
+bool coefficient_plane_fits(const lbm_params* p) {
+  const uint64_t es = p->storage == LBM_STORE_F64 ? 8 : 4;
+  return (uint64_t)p->ny * align_up((uint64_t)p->nx, kCoefTileW) * es < ((uint64_t)1 << 31);
+}
+
+// Device state kept as the six H2 coefficients (else the Q populations).
+bool uses_coefficients(const lbm_params* p) {
+  if (p->representation == LBM_REPR_COEFFICIENTS) return true;
+  return p->representation == LBM_REPR_AUTO && p->collision == LBM_COLL_REGULARIZED &&
+         p->nx >= kCoefTileW && coefficient_plane_fits(p);
+}
+
 int validate(const lbm_params* p, HostLattice* lat) {
   if (!p) return LBM_EINVAL;
   if (p->abi_version != LBM_ABI_VERSION) return LBM_EABI;
@@ -74,13 +87,21 @@ int validate(const lbm_params* p, HostLattice* lat) {
   if (p->collision != LBM_COLL_REGULARIZED && p->collision != LBM_COLL_BGK) return LBM_EINVAL;
   if (p->wall != LBM_WALL_BB) return LBM_EINVAL;
   if (p->far != LBM_FAR_WALL && p->far != LBM_FAR_EQ) return LBM_EINVAL;
-  if (p->tile != 0 && p->tile != 1 && p->tile != 2 && p->tile != 4) return LBM_EINVAL;
   if (p->representation > LBM_REPR_COEFFICIENTS) return LBM_EINVAL;
   if (p->representation == LBM_REPR_COEFFICIENTS && p->collision != LBM_COLL_REGULARIZED)
     return LBM_EINVAL;
   const int R = lat->R;
   if (p->nx < std::max(3, R) || p->ny < std::max(3, R)) return LBM_EINVAL;
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) return LBM_EINVAL;
+  if (p->representation == LBM_REPR_COEFFICIENTS && !coefficient_plane_fits(p))
+    return LBM_EINVAL;
+  // tile: cells per thread of the population kernel, or tile variant of the
+  // coefficient kernel
+  if (uses_coefficients(p)) {
+    if (p->tile > (uint32_t)kCoefKMax) return LBM_EINVAL;
+  } else if (p->tile != 0 && p->tile != 1 && p->tile != 2 && p->tile != 4) {
+    return LBM_EINVAL;
+  }
   if (!(p->tau > 0.5)) return LBM_EINVAL;  // rejects NaN too; +inf allowed
   if (!std::isfinite(p->omega) || !std::isfinite(p->u0)) return LBM_EINVAL;
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return LBM_EINVAL;
@@ -118,31 +139,6 @@ bool is_link(const lbm_params* p, const HostLattice& L, int x, int y, int q) {
   if (p->geometry == LBM_GEOM_PLATE) return sy < 0;
   if (p->geometry == LBM_GEOM_BOX) return in_body(p, sx, sy);
   return false;
-}
-
-// True if the coefficient kernel must take its wall path at cell (x, y):
-// within R of the body (box) or of a bounce-back wall (plate).
-bool is_edge_cell(const lbm_params* p, int R, int x, int y) {
-  if (p->geometry == LBM_GEOM_BOX)
-    return x >= p->box_x0 - R && x < p->box_x0 + p->box_lx + R && y >= p->box_y0 - R &&
-           y < p->box_y0 + p->box_ly + R;
-  if (p->geometry == LBM_GEOM_PLATE) return y < R || (p->far == LBM_FAR_WALL && y >= p->ny - R);
-  return false;
-}
-
-// Coefficient-kernel tiles that contain a wall cell.
-std::vector<char> edge_tiles(const lbm_params* p, const HostLattice& L, const Layout& lay) {
-  std::vector<char> e(lay.mntiles, 0);
-  const int tiles_y = lay.mntiles / lay.tiles_x;
-  for (int ty = 0; ty < tiles_y; ++ty)
-    for (int tx = 0; tx < lay.tiles_x; ++tx) {
-      bool any = false;
-      for (int y = ty * kMomTileH; y < std::min(p->ny, (ty + 1) * kMomTileH) && !any; ++y)
-        for (int x = tx * kMomTileW; x < std::min(p->nx, (tx + 1) * kMomTileW) && !any; ++x)
-          any = is_edge_cell(p, L.R, x, y);
-      e[ty * lay.tiles_x + tx] = any;
-    }
-  return e;
 }
 
 // Mirror cell of the bounce-back link arriving at fluid cell (x, y) along q
@@ -246,12 +242,12 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
     lay->ys = lay->pitch;
     lay->buf_elems = lay->qs * L.Q;
   }
-  lay->mom = p->representation == LBM_REPR_COEFFICIENTS ||
-             (p->representation == LBM_REPR_AUTO && p->collision == LBM_COLL_REGULARIZED &&
-              p->nx >= kMomTileW);
+  lay->mom = uses_coefficients(p);
   if (lay->mom) {
-    lay->tiles_x = (p->nx + kMomTileW - 1) / kMomTileW;
-    lay->mntiles = lay->tiles_x * ((p->ny + kMomTileH - 1) / kMomTileH);
+    lay->coef_k = p->tile ? (int32_t)p->tile : kCoefKDefault;
+    const int th = coef_tile_rows(lay->coef_k);
+    lay->tiles_x = (p->nx + kCoefTileW - 1) / kCoefTileW;
+    lay->mntiles = lay->tiles_x * ((p->ny + th - 1) / th);
     lay->mpitch = (int64_t)align_up(p->nx, 64);
     lay->mks = (int64_t)align_up((uint64_t)p->ny * lay->mpitch, 256) + 256;
     lay->mbuf_bytes = 6 * (uint64_t)lay->mks * es;
@@ -278,7 +274,6 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   if (lay->mom) {
     lay->mnwork = (int32_t)ordered_length(lay->mntiles, lay->tiles_x);
     lay->off_mwork = take(sizeof(WorkItem) * (uint64_t)lay->mnwork);
-    lay->off_mework = take(sizeof(WorkItem) * (uint64_t)lay->mntiles);
   }
   lay->off_solves = take(sizeof(int32_t));
   ForceTables ft;
@@ -365,20 +360,9 @@ int init_solver(lbm_solver* s) {
   for (int k = 0; k < 8; ++k) s->klat.w[k] = s->lat.lw.w_orbit[k];
   s->klat.theta = s->lat.lw.theta;
 
-  std::vector<WorkItem> work, mwork, mework;
+  std::vector<WorkItem> work, mwork;
   order_tiles(&work, 0, lay.ntiles, (p->nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
-  if (lay.mom) {
-    // interior list in XCD-aware order with the wall tiles made no-ops; the
-    // wall tiles in their own list
-    order_tiles(&mwork, 0, lay.mntiles, lay.tiles_x);
-    const std::vector<char> edge = edge_tiles(p, s->lat, lay);
-    for (WorkItem& w : mwork)
-      if (w.tile >= 0 && edge[w.tile]) {
-        mework.push_back(w);
-        w.tile = -1;
-      }
-    s->lay.menwork = (int32_t)mework.size();
-  }
+  if (lay.mom) order_tiles(&mwork, 0, lay.mntiles, lay.tiles_x);
   std::vector<Drive> drive((size_t)p->max_steps);
   for (int64_t n = 0; n < p->max_steps; ++n) {
     const double arg = p->omega * ((double)n + 0.5);
@@ -391,7 +375,6 @@ int init_solver(lbm_solver* s) {
   s->d_work = reinterpret_cast<WorkItem*>(b + lay.off_work);
   s->d_solves = reinterpret_cast<int32_t*>(b + lay.off_solves);
   s->d_mwork = lay.mom ? reinterpret_cast<WorkItem*>(b + lay.off_mwork) : nullptr;
-  s->d_mework = lay.mom ? reinterpret_cast<WorkItem*>(b + lay.off_mework) : nullptr;
 
   hipStream_t st = s->stream;
   int rc;
@@ -415,10 +398,6 @@ int init_solver(lbm_solver* s) {
     return rc;
   if (lay.mom) {
     if ((rc = hip_rc(hipMemcpyAsync(s->d_mwork, mwork.data(), sizeof(WorkItem) * mwork.size(),
-                                    hipMemcpyHostToDevice, st))))
-      return rc;
-    if (!mework.empty() &&
-        (rc = hip_rc(hipMemcpyAsync(s->d_mework, mework.data(), sizeof(WorkItem) * mework.size(),
                                     hipMemcpyHostToDevice, st))))
       return rc;
 
@@ -482,51 +461,6 @@ int create_common(const lbm_params* p, void* stream, void* dev_buf, uint64_t byt
 
 }  // namespace
 
-namespace lbm {
-
-int SideStream::ensure() {
-  if (stream) return LBM_OK;
-  // default priority on purpose: the side stream must not outrank the main one
-  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return LBM_EHIP;
-  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
-    return LBM_EHIP;
-  return LBM_OK;
-}
-
-void SideStream::release() {
-  if (stream) (void)hipStreamSynchronize(stream);
-  if (fork) (void)hipEventDestroy(fork);
-  if (join) (void)hipEventDestroy(join);
-  if (stream) (void)hipStreamDestroy(stream);
-  stream = nullptr;
-  fork = join = nullptr;
-}
-
-hipError_t launch_moment_pair(int Q, bool f64, const SolveDesc* descs, const WorkItem* interior,
-                              int ninterior, const WorkItem* edge, int nedge,
-                              const KernelLattice& lat, hipStream_t main, SideStream* side) {
-  hipError_t e;
-  if (nedge > 0) {
-    if (side->ensure() != LBM_OK) return hipErrorUnknown;
-    if ((e = hipEventRecord(side->fork, main)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess) return e;
-    if ((e = launch_moment(Q, f64, true, descs, edge, nedge, lat, side->stream)) != hipSuccess)
-      return e;
-    if ((e = hipEventRecord(side->join, side->stream)) != hipSuccess) return e;
-  }
-  if ((e = launch_moment(Q, f64, false, descs, interior, ninterior, lat, main)) != hipSuccess)
-    return e;
-  if (nedge > 0) return hipStreamWaitEvent(main, side->join, 0);
-  return hipSuccess;
-}
-
-}  // namespace lbm
-
-std::vector<char> solver_edge_tiles(const lbm_solver* s) {
-  return edge_tiles(&s->p, s->lat, s->lay);
-}
-
 // One step of a single solver: the population kernel, the population kernel
 // writing coefficients (first step after populations were loaded into a
 // coefficient solver), or the coefficient kernel; then the finalize.
@@ -544,8 +478,8 @@ int step_one(lbm_solver* s) {
                     s->stream);
     s->pop_pending = false;
   } else {
-    e = launch_moment_pair(Q, f64, s->d_desc, s->d_mwork, s->lay.mnwork, s->d_mework,
-                           s->lay.menwork, s->klat, s->stream, &s->side);
+    e = launch_coef(Q, f64, s->lay.coef_k, s->d_desc, s->d_mwork, s->lay.mnwork, s->klat,
+                    s->stream);
     mode = 1;
   }
   if (e != hipSuccess) return LBM_EHIP;
@@ -888,7 +822,6 @@ int lbm_set_state(lbm_solver* s, const void* host, uint64_t bytes) {
 int lbm_destroy(lbm_solver* s) {
   if (!s) return LBM_OK;
   int rc = hipStreamSynchronize(s->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
-  s->side.release();
   if (s->owned && hipFree(s->base) != hipSuccess) rc = LBM_EHIP;
   delete s;
   return rc;

@@ -21,10 +21,12 @@ struct lbm_batch {
   uint32_t storage = 0, collision = 0;
   int cpt = 1;
   bool have_pop = false;  // some member keeps populations (sets cpt)
+  int coef_k = 0;
+  bool have_mom = false;  // some member keeps coefficients (sets coef_k)
   // current launch set (members that still have steps to run)
   std::vector<lbm_solver*> active;
   bool dirty = true;
-  int nwork = 0, nmwork = 0, nmework = 0;  // population, coefficient interior and edge items
+  int nwork = 0, nmwork = 0;  // population-kernel and coefficient-kernel items
   SolveDesc* d_descs = nullptr;
   WorkItem* d_work = nullptr;   // population-kernel items, then coefficient-kernel items
   int32_t* d_solves = nullptr;
@@ -34,7 +36,6 @@ struct lbm_batch {
   int graph_steps = 0;
   int graph_chunk = 32;
   bool graphs_enabled = true;
-  SideStream side;   // wall tiles of the coefficient kernel
   // per-launch timing of the fused step kernel
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -74,21 +75,14 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
   b->active = act;
   b->dirty = false;
   std::vector<SolveDesc> descs;
-  std::vector<WorkItem> work, mwork, mework;
+  std::vector<WorkItem> work, mwork;
   std::vector<int32_t> solves;
   for (size_t i = 0; i < act.size(); ++i) {
     descs.push_back(act[i]->desc);
     solves.push_back((int32_t)i);
     const Layout& lay = act[i]->lay;
     if (lay.mom) {
-      const size_t at = mwork.size();
       order_tiles(&mwork, (int32_t)i, lay.mntiles, lay.tiles_x);
-      const std::vector<char> edge = solver_edge_tiles(act[i]);
-      for (size_t k = at; k < mwork.size(); ++k)
-        if (mwork[k].tile >= 0 && edge[mwork[k].tile]) {
-          mework.push_back(mwork[k]);
-          mwork[k].tile = -1;
-        }
     } else {
       order_tiles(&work, (int32_t)i, lay.ntiles,
                   (act[i]->p.nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
@@ -96,9 +90,7 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
   }
   b->nwork = (int)work.size();
   b->nmwork = (int)mwork.size();
-  b->nmework = (int)mework.size();
   work.insert(work.end(), mwork.begin(), mwork.end());
-  work.insert(work.end(), mework.begin(), mework.end());
   if (act.empty()) return LBM_OK;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EHIP;
   int rc;
@@ -146,10 +138,9 @@ int launch_one(lbm_batch* b) {
     if (b->nwork > 0)
       e = launch_step(b->Q, f64, bgk, b->cpt, false, b->d_descs, b->d_work, b->nwork, lat,
                       b->stream);
-    if (e == hipSuccess && (b->nmwork > 0 || b->nmework > 0))
-      e = launch_moment_pair(b->Q, f64, b->d_descs, b->d_work + b->nwork, b->nmwork,
-                             b->d_work + b->nwork + b->nmwork, b->nmework, lat, b->stream,
-                             &b->side);
+    if (e == hipSuccess && b->nmwork > 0)
+      e = launch_coef(b->Q, f64, b->coef_k, b->d_descs, b->d_work + b->nwork, b->nmwork, lat,
+                      b->stream);
     return e;
   };
   if (b->timing) {
@@ -174,7 +165,6 @@ int launch_one(lbm_batch* b) {
 // Capture graph_chunk steps of the current launch set into a graph.
 bool capture(lbm_batch* b) {
   if (b->stream == nullptr) return false;  // the null stream cannot be captured
-  if (b->nmework > 0 && b->side.ensure() != LBM_OK) return false;
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
@@ -227,11 +217,16 @@ int lbm_batch_add(lbm_batch* b, lbm_solver* s) {
              s->p.collision != b->collision) {
     return LBM_EINVAL;
   }
-  // members kept as populations share one population-kernel launch
+  // members kept as populations share one population-kernel launch, members
+  // kept as coefficients one coefficient-kernel launch
   if (!s->lay.mom) {
     if (b->have_pop && s->lay.cpt != b->cpt) return LBM_EINVAL;
     b->have_pop = true;
     b->cpt = s->lay.cpt;
+  } else {
+    if (b->have_mom && s->lay.coef_k != b->coef_k) return LBM_EINVAL;
+    b->have_mom = true;
+    b->coef_k = s->lay.coef_k;
   }
   b->members.push_back(s);
   b->dirty = true;
@@ -248,6 +243,7 @@ int lbm_batch_remove(lbm_batch* b, lbm_solver* s) {
   if (b->members.empty()) {
     b->Q = 0;
     b->have_pop = false;
+    b->have_mom = false;
   }
   return LBM_OK;
 }
@@ -346,7 +342,6 @@ int lbm_batch_destroy(lbm_batch* b) {
   if (!b) return LBM_OK;
   int rc = hipStreamSynchronize(b->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
   drop_graph(b);
-  b->side.release();
   for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
   if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_work) (void)hipFree(b->d_work);

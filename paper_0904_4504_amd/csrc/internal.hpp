@@ -14,8 +14,8 @@ namespace lbm {
 hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, bool outm, const SolveDesc* descs,
                        const WorkItem* work, int nwork, const KernelLattice& lat,
                        hipStream_t stream);
-hipError_t launch_moment(int Q, bool f64, bool edge, const SolveDesc* descs, const WorkItem* work,
-                         int nwork, const KernelLattice& lat, hipStream_t stream);
+hipError_t launch_coef(int Q, bool f64, int k, const SolveDesc* descs, const WorkItem* work,
+                       int nwork, const KernelLattice& lat, hipStream_t stream);
 hipError_t launch_finalize(bool f64, const SolveDesc* descs, const int32_t* solves, int nsolves,
                            int mode, hipStream_t stream);
 
@@ -38,12 +38,13 @@ struct Layout {
   int32_t ntiles = 0, cells_per_tile = kBlock, cpt = 1;
   int32_t nlinks = 0, nfcells = 0;
   uint64_t off_links = 0, off_fcells = 0;
-  // coefficient representation (mom): 64 x 8 tiles, six coefficient planes
+  // coefficient representation (mom): six coefficient planes, updated in
+  // tiles of kCoefTileW columns x coef_tile_rows(coef_k) rows
   bool mom = false;
-  int32_t tiles_x = 0, mntiles = 0;
+  int32_t coef_k = 0, tiles_x = 0, mntiles = 0;
   int64_t mpitch = 0, mks = 0;
-  uint64_t mbuf_bytes = 0, off_mwork = 0, off_mework = 0, off_mbuf[2] = {0, 0};
-  int32_t nwork = 0, mnwork = 0, menwork = 0;  // population, interior and edge work items
+  uint64_t mbuf_bytes = 0, off_mwork = 0, off_mbuf[2] = {0, 0};
+  int32_t nwork = 0, mnwork = 0;  // population-kernel and coefficient-kernel work items
   int64_t hist_cap = 0;
   uint64_t off_desc = 0, off_state = 0, off_work = 0, off_solves = 0, off_drive = 0,
            off_hist = 0, off_buf[2] = {0, 0};
@@ -60,24 +61,6 @@ struct lbm_solver;
 // One step of a single solver (population, population-to-coefficient or
 // coefficient kernel, then the finalize); defined in api.cpp.
 int step_one(lbm_solver* s);
-// Coefficient-kernel tiles of the solver that contain a wall cell.
-std::vector<char> solver_edge_tiles(const lbm_solver* s);
-
-namespace lbm {
-// A second stream on which the few wall tiles of the coefficient kernel run
-// concurrently with the interior tiles (forked from and joined back to the
-// main stream with events, so the pair can also be captured in a graph).
-struct SideStream {
-  hipStream_t stream = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  int ensure();   // create on first use; LBM_OK or LBM_EHIP
-  void release();
-};
-// Interior tiles on `main`, wall tiles on the side stream, joined on `main`.
-hipError_t launch_moment_pair(int Q, bool f64, const SolveDesc* descs, const WorkItem* interior,
-                              int ninterior, const WorkItem* edge, int nedge,
-                              const KernelLattice& lat, hipStream_t main, SideStream* side);
-}  // namespace lbm
 
 struct lbm_solver {
   // solver state; host fields mirror the device counters after a sync
@@ -92,9 +75,7 @@ struct lbm_solver {
   int device = 0;
   int64_t steps = 0;          // steps enqueued
   bool pop_pending = false;   // coefficient solver whose current state is populations
-  lbm::WorkItem* d_mwork = nullptr;   // coefficient kernel: interior tiles (edge ones no-op)
-  lbm::WorkItem* d_mework = nullptr;  // coefficient kernel: tiles with wall links
-  lbm::SideStream side;
+  lbm::WorkItem* d_mwork = nullptr;   // coefficient kernel: tiles in XCD-aware order
   lbm::SolveDesc desc{};      // host copy (device pointers)
   lbm::SolveDesc* d_desc = nullptr;
   lbm::WorkItem* d_work = nullptr;

@@ -7,8 +7,13 @@
 namespace lbm {
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
-constexpr int kMomTileW = 64;    // coefficient kernel: tile width (one wavefront per row)
-constexpr int kMomTileH = 4;     // coefficient kernel: tile height (one row per wavefront)
+constexpr int kCoefTileW = 64;   // coefficient kernel: tile width (one column per lane)
+constexpr int kCoefKMax = 3;     // coefficient kernel: tile variants K = 1..3
+constexpr int kCoefKDefault = 2;
+
+// Rows of a coefficient-kernel tile of variant K: four wavefronts of K rows
+// each (K cells per thread).
+__host__ __device__ constexpr int coef_tile_rows(int K) { return 4 * K; }
 constexpr int kMaxSlots = 1 << 20;
 
 enum Geom : int32_t { GEOM_PLATE = 0, GEOM_BOX = 1, GEOM_PERIODIC = 2 };
@@ -56,7 +61,7 @@ struct SolveDesc {
                              // n reads mbuf[n & 1]; coefficient k of cell (x, y) at
                              // k*mks + y*mys + x (null when the solver keeps populations)
   int64_t mks, mys;
-  int32_t tiles_x, pad2;
+  int32_t tiles_x, pad2;          // coefficient kernel: tiles per row of tiles
   int64_t qs;                // elements between the populations of one cell
   int64_t ys;                // elements between rows
   int64_t max_steps;
