@@ -19,6 +19,8 @@ algorithmic HBM bandwidth beside it; and the CPU oracle timed on a bounded
 sample on this host.
 
     python bench.py [--steps K] [--warmup W] [--workload beam_box|plate_sweep]
+    python bench.py --workload batch_sweep   # sweep solves/s, batched vs plain loop
+    python bench.py --workload serving       # p50/p99 latency, batched vs plain loop
 """
 import argparse
 import hashlib
@@ -112,6 +114,99 @@ def cpu_baseline(solve, budget_s):
                       f"rest, FP64 oracle, OpenMP over rows on {cores} threads, {dt:.1f} s"}
 
 
+def sweep_mode(a):
+    """Batched sweep vs the plain one-solve-at-a-time loop on a bounded sample
+    of the 256-solve batch workload: the first `--sweep-solves` solves of the
+    seeded draw, each run for `--sweep-steps` steps (lock-in over the second
+    half).  Prints solves/s and MLUPS of both and the largest relative
+    impedance difference between them."""
+    import torch
+    import lbm_inputs as W
+    import paper_0904_4504_amd as P
+    solves = [s.scaled(a.sweep_steps, a.sweep_steps // 2)
+              for s in W.batch_sweep(count=a.sweep_solves)]
+    cells = sum(s.fluid_cells for s in solves) * a.sweep_steps
+    stream = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(stream):
+        # warm-up: one small solve through both paths (code objects, graphs)
+        warm = solves[0].scaled(64, 32)
+        with P.Solver(P.params_from_solve(warm), stream=stream) as sv:
+            sv.step(64)
+            sv.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solvers = [P.Solver(P.params_from_solve(s), stream=stream) for s in solves]
+        batch = P.Batch(stream)
+        for sv in solvers:
+            batch.add(sv)
+        batch.step(a.sweep_steps)
+        batch.synchronize()
+        zb = [sv.impedance() for sv in solvers]
+        batch.close()
+        for sv in solvers:
+            sv.close()
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        zp = []
+        for s in solves:
+            with P.Solver(P.params_from_solve(s), stream=stream) as sv:
+                sv.step(a.sweep_steps)
+                sv.synchronize()
+                zp.append(sv.impedance())
+        tp = time.perf_counter() - t0
+    dz = max(abs(x["Z"] - y["Z"]) / abs(y["Z"]) for x, y in zip(zb, zp))
+    out = {"metric": "sweep solves/s (batched vs plain loop)", "value": len(solves) / tb,
+           "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "plain_value": len(solves) / tp, "speedup": tp / tb,
+           "batched_mlups": cells / tb / 1e6, "plain_mlups": cells / tp / 1e6,
+           "max_rel_dZ_batched_vs_plain": dz,
+           "config": {"workload": f"batch_sweep sample: first {len(solves)} of the seeded "
+                                  f"256-solve draw (sides 256-2048, aspect 1/2/4, plate or box, "
+                                  f"tau*omega 1e-2..1e2), {a.sweep_steps} steps each, D2Q37 FP32",
+                      "wall_s_batched": tb, "wall_s_plain": tp,
+                      "solver_create_included": True}}
+    print(json.dumps(out), flush=True)
+
+
+def serving_mode(a):
+    """Continuous batching vs the plain loop on the serving mix (1 box : 4
+    plates), with drive periods of `--serve-period` steps (10 + 10 periods per
+    request).  Capacity is measured with every request queued at t = 0; the
+    Poisson traces then run at 0.5, 0.8 and 0.95 of it through both paths."""
+    import torch
+    import lbm_inputs as W
+    from paper_0904_4504_amd import serve as S
+    torch.cuda.set_device(0)
+    n = a.serve_requests
+    burst = [(0.0, s) for _, s in W.serving_trace(1.0, n, period=a.serve_period)]
+    # warm-up
+    S.serve(burst[:4], chunk=a.serve_chunk)
+    _, cap = S.serve(burst, chunk=a.serve_chunk)
+    capacity = cap["solves_per_s"]
+    rates = []
+    for f in (0.5, 0.8, 0.95):
+        trace = W.serving_trace(f * capacity, n, period=a.serve_period)
+        rb, sb = S.serve(trace, chunk=a.serve_chunk)
+        rp, sp = S.serve_plain(trace)
+        dz = max(abs(x.result["Z"] - y.result["Z"]) / abs(y.result["Z"]) for x, y in zip(rb, rp))
+        rates.append({"load": f, "rate_per_s": f * capacity,
+                      "batched": {k: sb[k] for k in ("solves_per_s", "latency_p50_s",
+                                                     "latency_p99_s", "wall_s")},
+                      "plain": {k: sp[k] for k in ("solves_per_s", "latency_p50_s",
+                                                   "latency_p99_s", "wall_s")},
+                      "max_rel_dZ_batched_vs_plain": dz})
+    out = {"metric": "serving solves/s and p50/p99 latency (continuous batching vs plain loop)",
+           "value": capacity, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "rates": rates,
+           "config": {"workload": f"serving mix: {n} requests per rate, 1 box (1024x1024, body "
+                                  f"32x16) : 4 plates (4 x 1024..8192), tau*omega 1e-3..1e3, "
+                                  f"period {a.serve_period} steps, 10 + 10 periods per request, "
+                                  f"D2Q37 FP32, HBM budget 200 GB",
+                      "chunk_steps": a.serve_chunk}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +220,11 @@ def main():
     ap.add_argument("--tile", type=int, default=0,
                     help="kernel tile (cells per thread of the population or the coefficient "
                          "kernel); 0 = library default")
+    ap.add_argument("--sweep-solves", type=int, default=32)
+    ap.add_argument("--sweep-steps", type=int, default=2048)
+    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-period", type=int, default=128)
+    ap.add_argument("--serve-chunk", type=int, default=128)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solves of a sweep are independent and would "
@@ -136,6 +236,10 @@ def main():
     import paper_0904_4504_amd as P
 
     torch.cuda.set_device(0)
+    if a.workload == "batch_sweep":
+        return sweep_mode(a)
+    if a.workload == "serving":
+        return serving_mode(a)
     solves, desc = workload(a.workload, a.steps, a.warmup)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
