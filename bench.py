@@ -40,7 +40,8 @@ CSRC = os.path.join(ROOT, "paper_0904_4504_amd", "csrc")
 KERNELS = {
     1: ("lbm::step_kernel<D2Q37, float, false, 256, false>", "kernels.hip",
         "step_kernel_beam_box_counters.json"),
-    2: ("lbm::coef_kernel<D2Q37, float, {rb}>", "coef.hip", "coef_kernel_beam_box_counters.json"),
+    2: ("lbm::coef_kernel<D2Q37, float, {rb}, false>", "coef.hip",
+        "coef_kernel_beam_box_counters.json"),
 }
 # FP32 arithmetic per lattice update of the coefficient kernel's interior path
 # (D2Q37, FMA = 2): 37 populations evaluated from their source cells' six
@@ -213,7 +214,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="beam_box")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--representation", type=int, default=0,
                     help="0 automatic, 1 populations, 2 H2 coefficients")

@@ -68,8 +68,14 @@ enum { LBM_STORE_F64 = 0, LBM_STORE_F32_DEV = 1 };
  * f_i = f_i^eq + (1 - 1/tau)(f_i^adv - f_i^eq) (eq. LBGK, for checks). */
 enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
 
-/* Wall model of the moving body: bounce-back (eq. BB). */
-enum { LBM_WALL_BB = 0 };
+/* Wall model of the moving body: bounce-back (eq. BB), or diffuse
+ * scattering (eq. DS; plate geometry only): a population arriving from the
+ * moving wall in column x is the H2 equilibrium (eq. feq_h2) at the wall
+ * velocity with the wall density rho_w(x) that balances the mass of the
+ * populations of column x crossing the wall in that step (zero normal mass
+ * flux, eq. kinetic_bc; the crossing populations are those bounce-back
+ * would reflect into column x).  The stationary far wall stays bounce-back. */
+enum { LBM_WALL_BB = 0, LBM_WALL_DS = 1 };
 
 /* Geometry.
  *  PLATE:    x periodic (nx cells); the moving wall lies half-way below row
@@ -98,7 +104,7 @@ typedef struct lbm_params {
   uint32_t lattice;      /* LBM_D2Q9 or LBM_D2Q37 */
   uint32_t storage;      /* LBM_STORE_* */
   uint32_t collision;    /* LBM_COLL_* */
-  uint32_t wall;         /* LBM_WALL_BB */
+  uint32_t wall;         /* LBM_WALL_BB or LBM_WALL_DS (plate only) */
   uint32_t geometry;     /* LBM_GEOM_* */
   uint32_t far;          /* LBM_FAR_* */
   uint32_t tile;         /* kernel tile.  Populations: 0 (= 1), 1, 2 or 4; one workgroup of

@@ -54,6 +54,7 @@ class Solve:
     window_count: int = 0
     storage: str = "f32dev"    # "f64" or "f32dev"
     collision: str = "regularized"
+    wall: str = "bb"           # model of the moving wall: "bb" or "ds" (plate only)
     noise: float = 0.0
     seed: int = 0
     tau_omega: float = float("nan")

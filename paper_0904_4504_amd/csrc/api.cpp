@@ -85,7 +85,8 @@ int validate(const lbm_params* p, HostLattice* lat) {
   if (!host_lattice((int)p->lattice, lat)) return LBM_EINVAL;
   if (p->storage != LBM_STORE_F64 && p->storage != LBM_STORE_F32_DEV) return LBM_EINVAL;
   if (p->collision != LBM_COLL_REGULARIZED && p->collision != LBM_COLL_BGK) return LBM_EINVAL;
-  if (p->wall != LBM_WALL_BB) return LBM_EINVAL;
+  if (p->wall != LBM_WALL_BB && p->wall != LBM_WALL_DS) return LBM_EINVAL;
+  if (p->wall == LBM_WALL_DS && p->geometry != LBM_GEOM_PLATE) return LBM_EINVAL;
   if (p->far != LBM_FAR_WALL && p->far != LBM_FAR_EQ) return LBM_EINVAL;
   if (p->representation > LBM_REPR_COEFFICIENTS) return LBM_EINVAL;
   if (p->representation == LBM_REPR_COEFFICIENTS && p->collision != LBM_COLL_REGULARIZED)
@@ -164,15 +165,21 @@ void mirror_of(const lbm_params* p, const HostLattice& L, int x, int y, int q, i
 // the deviation part becomes the link list (population state) or, per mirror
 // cell, two 6-vectors acting on the cell's H2 coefficients (coefficient state:
 // df_opp(x_p) = w_i (a0 - vx bx - vy by + vx^2 cxx + vx vy cxy + vy^2 cyy)).
+// At a diffuse wall (eq. DS) the arrival f_i^adv is the wall's emission: the
+// tables then carry -v_i df_opp(x_p) and the crossing mass df_opp(x_p), and
+// the emission's share follows from the lattice sums in `ds` (finalize).
 struct ForceTables {
   std::vector<ForceLink> links;
   std::vector<ForceCell> cells;
   double fstatic[2] = {0, 0}, kladd[2] = {0, 0};
+  double ds[6] = {0, 0, 0, 0, 0, 0};
 };
 
 void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout& lay,
                         ForceTables* t) {
   long double sx = 0, sy = 0, kx = 0, ky = 0;
+  const bool diffuse = p->wall == LBM_WALL_DS;
+  const long double mw = diffuse ? 1.0L : 2.0L;  // weight of the reflected deviation
   std::unordered_map<int64_t, size_t> index;  // mirror cell -> position in t->cells
   auto cell_for = [&](int px, int py) -> ForceCell& {
     const int64_t key = (int64_t)py * p->nx + px;
@@ -200,11 +207,14 @@ void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout&
         const int vx = L.vx[q], vy = L.vy[q];
         sx -= vx * 2.0L * w * p->rho0;
         sy -= vy * 2.0L * w * p->rho0;
-        kx -= vx * 2.0L * w * p->rho0 * vx / L.lw.theta_ld;
-        ky -= vy * 2.0L * w * p->rho0 * vx / L.lw.theta_ld;
+        if (!diffuse) {
+          kx -= vx * 2.0L * w * p->rho0 * vx / L.lw.theta_ld;
+          ky -= vy * 2.0L * w * p->rho0 * vx / L.lw.theta_ld;
+        }
         int px, py;
         mirror_of(p, L, x, y, q, &px, &py);
-        t->links.push_back(ForceLink{L.opp[q] * lay.qs + py * lay.ys + px, -2.0 * vx, -2.0 * vy});
+        t->links.push_back(ForceLink{L.opp[q] * lay.qs + py * lay.ys + px, (double)(-mw * vx),
+                                     (double)(-mw * vy), diffuse ? 1.0 : 0.0});
         if (lay.mom) {
           ForceCell& fc = cell_for(px, py);
           // basis of the opposite direction -v at the mirror cell
@@ -212,8 +222,9 @@ void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout&
                                     (long double)vx * vx, (long double)vx * vy,
                                     (long double)vy * vy};
           for (int k = 0; k < 6; ++k) {
-            fc.wx[k] += (double)(-2.0L * vx * w * g[k]);
-            fc.wy[k] += (double)(-2.0L * vy * w * g[k]);
+            fc.wx[k] += (double)(-mw * vx * w * g[k]);
+            fc.wy[k] += (double)(-mw * vy * w * g[k]);
+            if (diffuse) fc.wm[k] += (double)(w * g[k]);
           }
         }
       }
@@ -222,6 +233,28 @@ void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout&
   t->fstatic[1] = (double)sy;
   t->kladd[0] = (double)kx;
   t->kladd[1] = (double)ky;
+  if (diffuse) {
+    // lattice sums over the directions the wall emits (v_y > 0)
+    const long double th = L.lw.theta_ld;
+    long double a1 = 0, a2 = 0, bx = 0, by0 = 0, by2 = 0;
+    for (int q = 0; q < L.Q; ++q) {
+      if (L.vy[q] <= 0) continue;
+      const long double w = L.lw.w_orbit_ld[L.orbit[q]];
+      const long double vx = L.vx[q], vy = L.vy[q];
+      const long double e2 = vx * vx / (2 * th * th) - 1 / (2 * th);
+      a1 += vy * w;
+      a2 += vy * w * e2;
+      bx += vy * vx * vx * w / th;
+      by0 += vy * vy * w;
+      by2 += vy * vy * w * e2;
+    }
+    t->ds[0] = (double)a1;
+    t->ds[1] = (double)a2;
+    t->ds[2] = (double)bx;
+    t->ds[3] = (double)by0;
+    t->ds[4] = (double)by2;
+    t->ds[5] = (double)((long double)p->nx * p->rho0);
+  }
 }
 
 void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
@@ -349,6 +382,8 @@ int init_solver(lbm_solver* s) {
   d.fstatic[1] = ft.fstatic[1];
   d.kladd[0] = ft.kladd[0];
   d.kladd[1] = ft.kladd[1];
+  d.wall = p->wall == LBM_WALL_DS ? WALL_DS : WALL_BB;
+  for (int k = 0; k < 6; ++k) d.ds[k] = ft.ds[k];
   if (lay.mom) {
     d.mbuf[0] = b + lay.off_mbuf[0];
     d.mbuf[1] = b + lay.off_mbuf[1];
@@ -478,8 +513,8 @@ int step_one(lbm_solver* s) {
                     s->stream);
     s->pop_pending = false;
   } else {
-    e = launch_coef(Q, f64, s->lay.coef_k, s->d_desc, s->d_mwork, s->lay.mnwork, s->klat,
-                    s->stream);
+    e = launch_coef(Q, f64, s->lay.coef_k, s->p.wall == LBM_WALL_DS, s->d_desc, s->d_mwork,
+                    s->lay.mnwork, s->klat, s->stream);
     mode = 1;
   }
   if (e != hipSuccess) return LBM_EHIP;

@@ -27,6 +27,7 @@ struct lbm_batch {
   std::vector<lbm_solver*> active;
   bool dirty = true;
   int nwork = 0, nmwork = 0;  // population-kernel and coefficient-kernel items
+  bool any_ds = false;        // a coefficient member of the launch has a diffuse wall
   SolveDesc* d_descs = nullptr;
   WorkItem* d_work = nullptr;   // population-kernel items, then coefficient-kernel items
   int32_t* d_solves = nullptr;
@@ -77,7 +78,9 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
   std::vector<SolveDesc> descs;
   std::vector<WorkItem> work, mwork;
   std::vector<int32_t> solves;
+  b->any_ds = false;
   for (size_t i = 0; i < act.size(); ++i) {
+    if (act[i]->lay.mom && act[i]->p.wall == LBM_WALL_DS) b->any_ds = true;
     descs.push_back(act[i]->desc);
     solves.push_back((int32_t)i);
     const Layout& lay = act[i]->lay;
@@ -139,8 +142,8 @@ int launch_one(lbm_batch* b) {
       e = launch_step(b->Q, f64, bgk, b->cpt, false, b->d_descs, b->d_work, b->nwork, lat,
                       b->stream);
     if (e == hipSuccess && b->nmwork > 0)
-      e = launch_coef(b->Q, f64, b->coef_k, b->d_descs, b->d_work + b->nwork, b->nmwork, lat,
-                      b->stream);
+      e = launch_coef(b->Q, f64, b->coef_k, b->any_ds, b->d_descs, b->d_work + b->nwork,
+                      b->nmwork, lat, b->stream);
     return e;
   };
   if (b->timing) {

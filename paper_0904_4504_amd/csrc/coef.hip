@@ -33,6 +33,7 @@
 #include "device_util.hpp"
 #include "lattice.hpp"
 #include "solver.hpp"
+#include "walls.hpp"
 
 namespace lbm {
 
@@ -105,18 +106,38 @@ constexpr bool source_used(int vx, int iy) {
 // Bounce-back contributions of the wall links of fluid cell (x, y): each link
 // population arrived as zero from the stream; add f_opp(x_p) (+ the
 // moving-wall term) and its moments.
-template <class L, typename S>
+template <class L, typename S, bool DSW>
 __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<const S> min,
-                                                      int x, int y, S ladd, const KernelLattice& lat) {
+                                                      int x, int y, S ladd, double U,
+                                                      const KernelLattice& lat) {
   const int64_t ks = d.mks;
   const int ys = (int)d.mys;
   const bool is_box = d.geom == GEOM_BOX;
+  // diffuse wall: deviation of the mass crossing the wall in column x, from
+  // the coefficients of rows 0 .. R-1 (population q at row r crosses when
+  // r < -v_qy)
+  double cm = 0.0;
+  if (DSW && d.wall == WALL_DS && d.geom == GEOM_PLATE && y < L::R) {
+    static_for<0, L::R>([&](auto rc) __attribute__((always_inline)) {
+      constexpr int r = decltype(rc)::value;
+      const int g = r * ys + x;
+      const double c0 = min[g], c1 = min[ks + g], c2 = min[2 * ks + g], c3 = min[3 * ks + g],
+                   c4 = min[4 * ks + g], c5 = min[5 * ks + g];
+      static_for<0, L::Q>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int vx = L::vx[q], vy = L::vy[q];
+        if constexpr (vy < -r)
+          cm += lat.w[L::orbit[q]] *
+                (c0 + vx * c1 + vy * c2 + vx * vx * c3 + vx * vy * c4 + vy * vy * c5);
+      });
+    });
+  }
   static_for<0, L::Q>([&](auto qc) __attribute__((always_inline)) {
     constexpr int q = decltype(qc)::value;
     constexpr int vx = L::vx[q], vy = L::vy[q];
     const int sx = x - vx, sy = y - vy;
     int px = -1, py = -1;
-    bool moving = false;
+    bool moving = false, diffuse = false;
     if (is_box) {
       if (sx >= d.bx0 && sx < d.bx1 && sy >= d.by0 && sy < d.by1) {
         px = x < d.bx0 ? 2 * d.bx0 - 1 - sx : (x >= d.bx1 ? 2 * d.bx1 - 1 - sx : x);
@@ -129,6 +150,7 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<c
           px = x;
           py = -1 - sy;
           moving = true;
+          diffuse = DSW && d.wall == WALL_DS;
         }
       }
       if constexpr (vy < 0) {
@@ -139,15 +161,20 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<c
       }
     }
     if (py >= 0) {
-      const int g = py * ys + px;
-      // population of -v at the mirror cell
-      S p = min[g];
-      if constexpr (vx != 0) p += S(-vx) * min[ks + g] + S(vx * vx) * min[3 * ks + g];
-      if constexpr (vy != 0) p += S(-vy) * min[2 * ks + g] + S(vy * vy) * min[5 * ks + g];
-      if constexpr (vx * vy != 0) p += S(vx * vy) * min[4 * ks + g];
       const S wq = (S)lat.w[L::orbit[q]];
-      S f = wq * p;
-      if (moving) f += (wq * S(vx)) * ladd;
+      S f;
+      if (DSW && diffuse) {
+        f = (S)ds_arrival<vx>(d, U, cm, lat.w[L::orbit[q]], lat.theta);
+      } else {
+        const int g = py * ys + px;
+        // population of -v at the mirror cell
+        S p = min[g];
+        if constexpr (vx != 0) p += S(-vx) * min[ks + g] + S(vx * vx) * min[3 * ks + g];
+        if constexpr (vy != 0) p += S(-vy) * min[2 * ks + g] + S(vy * vy) * min[5 * ks + g];
+        if constexpr (vx * vy != 0) p += S(vx * vy) * min[4 * ks + g];
+        f = wq * p;
+        if (moving) f += (wq * S(vx)) * ladd;
+      }
       m.v[0] += f;
       if constexpr (vx != 0) m.v[1] += S(vx) * f;
       if constexpr (vy != 0) m.v[2] += S(vy) * f;
@@ -218,7 +245,7 @@ __device__ __forceinline__ void stage_load(const SolveDesc* __restrict__ descs, 
 
 // Moments, bounce-back corrections, collision and store of the RB cells of
 // this thread, from the staged tile in LDS.
-template <class L, typename S, int RB>
+template <class L, typename S, int RB, bool DSW>
 __device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
                                              const S (&C)[6][CoefTile<L, RB>::NC],
                                              const KernelLattice& lat) {
@@ -337,7 +364,7 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
     if (is_box && y >= by0 && y < by1 && x >= bx0 && x < bx1) continue;  // solid
     if (wave_has_wall) {
       const bool near = (y >= wy0 && y < wy1 && x >= wx0 && x < wx1) || (far_band && y >= ny - R);
-      if (near) m = add_links<L, S>(m, d, min, x, y, ladd, lat);
+      if (near) m = add_links<L, S, DSW>(m, d, min, x, y, ladd, d.drive[n].u, lat);
     }
     const S drho = m.v[0], jx = m.v[1], jy = m.v[2];
     const S rho = rho0 + drho;
@@ -363,7 +390,9 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
   }
 }
 
-template <class L, typename S, int RB>
+// DSW: with the diffuse-scattering wall (a separate instantiation, so that
+// the bounce-back kernel carries none of its code).
+template <class L, typename S, int RB, bool DSW>
 __global__ __launch_bounds__(256) void coef_kernel(const SolveDesc* __restrict__ descs,
                                                    const WorkItem* __restrict__ work,
                                                    KernelLattice lat) {
@@ -385,39 +414,45 @@ __global__ __launch_bounds__(256) void coef_kernel(const SolveDesc* __restrict__
       for (int k = 0; k < 6; ++k) C[k][i] = c[it][k];
   }
   __syncthreads();
-  compute_tile<L, S, RB>(descs[wi.solve], wi.tile, C, lat);
+  compute_tile<L, S, RB, DSW>(descs[wi.solve], wi.tile, C, lat);
 }
 
 template <class L, typename S, int RB>
-static hipError_t launch_rb(const SolveDesc* descs, const WorkItem* work, int nwork,
+static hipError_t launch_rb(bool ds, const SolveDesc* descs, const WorkItem* work, int nwork,
                             const KernelLattice& lat, hipStream_t stream) {
-  hipLaunchKernelGGL((coef_kernel<L, S, RB>), dim3(nwork), dim3(256), 0, stream, descs, work, lat);
+  if (ds)
+    hipLaunchKernelGGL((coef_kernel<L, S, RB, true>), dim3(nwork), dim3(256), 0, stream, descs,
+                       work, lat);
+  else
+    hipLaunchKernelGGL((coef_kernel<L, S, RB, false>), dim3(nwork), dim3(256), 0, stream, descs,
+                       work, lat);
   return hipGetLastError();
 }
 
 template <class L, typename S>
-static hipError_t launch_coef_t(int k, const SolveDesc* descs, const WorkItem* work, int nwork,
-                                const KernelLattice& lat, hipStream_t stream) {
+static hipError_t launch_coef_t(int k, bool ds, const SolveDesc* descs, const WorkItem* work,
+                                int nwork, const KernelLattice& lat, hipStream_t stream) {
   switch (k) {
     case 1:
-      return launch_rb<L, S, 1>(descs, work, nwork, lat, stream);
+      return launch_rb<L, S, 1>(ds, descs, work, nwork, lat, stream);
     case 2:
-      return launch_rb<L, S, 2>(descs, work, nwork, lat, stream);
+      return launch_rb<L, S, 2>(ds, descs, work, nwork, lat, stream);
     case 3:
-      return launch_rb<L, S, 3>(descs, work, nwork, lat, stream);
+      return launch_rb<L, S, 3>(ds, descs, work, nwork, lat, stream);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_coef(int Q, bool f64, int k, const SolveDesc* descs, const WorkItem* work,
-                       int nwork, const KernelLattice& lat, hipStream_t stream) {
+hipError_t launch_coef(int Q, bool f64, int k, bool ds, const SolveDesc* descs,
+                       const WorkItem* work, int nwork, const KernelLattice& lat,
+                       hipStream_t stream) {
   if (nwork <= 0) return hipSuccess;
   if (Q == 9)
-    return f64 ? launch_coef_t<D2Q9, double>(k, descs, work, nwork, lat, stream)
-               : launch_coef_t<D2Q9, float>(k, descs, work, nwork, lat, stream);
-  return f64 ? launch_coef_t<D2Q37, double>(k, descs, work, nwork, lat, stream)
-             : launch_coef_t<D2Q37, float>(k, descs, work, nwork, lat, stream);
+    return f64 ? launch_coef_t<D2Q9, double>(k, ds, descs, work, nwork, lat, stream)
+               : launch_coef_t<D2Q9, float>(k, ds, descs, work, nwork, lat, stream);
+  return f64 ? launch_coef_t<D2Q37, double>(k, ds, descs, work, nwork, lat, stream)
+             : launch_coef_t<D2Q37, float>(k, ds, descs, work, nwork, lat, stream);
 }
 
 }  // namespace lbm

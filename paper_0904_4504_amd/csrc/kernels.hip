@@ -35,6 +35,7 @@
 #include "device_util.hpp"
 #include "lattice.hpp"
 #include "solver.hpp"
+#include "walls.hpp"
 
 namespace lbm {
 
@@ -45,7 +46,8 @@ namespace lbm {
 // the same input state by the finalize kernel.
 template <class L, typename S, int q>
 __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__ fin, int x,
-                                       int y, double ladd, double wq) {
+                                       int y, double ladd, double wq, double U, double cm,
+                                       double theta) {
   constexpr int vx = L::vx[q], vy = L::vy[q];
   constexpr int o = opposite<L>(q);
   const int nx = d.nx, ny = d.ny;
@@ -63,7 +65,9 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
     sx -= sx >= nx ? nx : 0;
     if constexpr (vy > 0) {
       if (sy < 0) {
-        // crossed the moving wall at y = -1/2: retrace in y, keep x
+        // from the moving wall at y = -1/2: diffuse emission, or bounce-back
+        // (retrace in y, keep x)
+        if (d.wall == WALL_DS) return (S)ds_arrival<vx>(d, U, cm, wq, theta);
         const int py = -1 - sy;
         return fin[o * qs + py * ys + x] + (S)(wq * vx * ladd);
       }
@@ -121,10 +125,19 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
       f[q] = fin[q * qs + idx - (L::vy[q] * ys + L::vx[q])];
     });
   } else if (fluid) {
-    const double ladd = d.ladd_scale * d.drive[n].u;
+    const double U = d.drive[n].u;
+    const double ladd = d.ladd_scale * U;
+    // diffuse wall: deviation of the mass crossing the wall in column x
+    double cm = 0.0;
+    if (d.wall == WALL_DS && d.geom == GEOM_PLATE && y < R)
+      static_for<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (L::vy[q] < 0)
+          for (int r = 0; r < -L::vy[q]; ++r) cm += (double)fin[q * qs + r * ys + x];
+      });
     static_for<0, Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      f[q] = pull_edge<L, S, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]]);
+      f[q] = pull_edge<L, S, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], U, cm, lat.theta);
     });
   } else {
     static_for<0, Q>([&](auto qc) { f[decltype(qc)::value] = S(0); });
@@ -224,7 +237,9 @@ __global__ __launch_bounds__(BS) void step_kernel(const SolveDesc* __restrict__ 
 // f_i^adv(x)) = -v_i (2 f_opp(x_p) + 2 w_i rho0 (v_i.U_w)/theta) (+ the rest
 // state), so F_n = F_static + K_ladd U_w(n) + sum over links of the reflected
 // populations of step n's input state, read here from the step's input buffer
-// (untouched by the step) and summed in a fixed order in FP64.  Then append
+// (untouched by the step) and summed in a fixed order in FP64.  At a diffuse
+// wall (eq. DS) f_i^adv is the wall's emission, which depends on the same
+// input state only through the crossing mass of each column.  Then append
 // F_n to the history ring, accumulate the lock-in sums when n lies in the
 // window, and advance the step counter.
 // mode 0: the step read populations; 1: coefficients; 2: per solve,
@@ -234,7 +249,7 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
   SolveState* st = d.state;
   const int64_t n = st->step;
   const bool coeffs = mode == 1 || (mode == 2 && d.mbuf[0] != nullptr);
-  double fx = 0.0, fy = 0.0;
+  double fx = 0.0, fy = 0.0, fm = 0.0;
   if (coeffs) {
     const S* __restrict__ c = static_cast<const S*>(d.mbuf[n & 1]);
     const int64_t ks = d.mks;
@@ -245,6 +260,7 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
         const double v = (double)c[k * ks + fc.off];
         fx += fc.wx[k] * v;
         fy += fc.wy[k] * v;
+        fm += fc.wm[k] * v;
       }
     }
   } else {
@@ -254,27 +270,42 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
       const double v = (double)f[l.off];
       fx += l.wx * v;
       fy += l.wy * v;
+      fm += l.wm * v;
     }
   }
-  __shared__ double red[2][kBlock / 64];
+  __shared__ double red[3][kBlock / 64];
   fx = wave_sum(fx);
   fy = wave_sum(fy);
+  fm = wave_sum(fm);
   const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     red[0][wave] = fx;
     red[1][wave] = fy;
+    red[2][wave] = fm;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     const Drive dr = d.drive[n];
-    double sx = 0.0, sy = 0.0;
+    double sx = 0.0, sy = 0.0, sm = 0.0;
 #pragma unroll
     for (int k = 0; k < kBlock / 64; ++k) {
       sx += red[0][k];
       sy += red[1][k];
+      sm += red[2][k];
     }
     fx = d.fstatic[0] + d.kladd[0] * dr.u + sx;
     fy = d.fstatic[1] + d.kladd[1] * dr.u + sy;
+    if (d.wall == WALL_DS) {
+      // the diffuse emissions' share of -sum v_i f_i^adv over the links:
+      // every column emits w_i rho_w E_i(U) along each link, rho_w from the
+      // column's crossing mass (rest part nx rho0 A1, deviation sm)
+      const double U = dr.u, uu = U * U;
+      const double emit = d.ds[0] + uu * d.ds[1];
+      const double nr = d.ds[5];
+      fx -= (nr * d.ds[0] * U * d.ds[2] + sm * U * d.ds[2]) / emit;
+      fy -= (nr * uu * (d.ds[0] * d.ds[4] - d.ds[1] * d.ds[3]) + sm * (d.ds[3] + uu * d.ds[4])) /
+            emit;
+    }
     const int64_t h = n % d.hist_cap;
     d.hist[2 * h] = fx;
     d.hist[2 * h + 1] = fy;

@@ -18,6 +18,7 @@ constexpr int kMaxSlots = 1 << 20;
 
 enum Geom : int32_t { GEOM_PLATE = 0, GEOM_BOX = 1, GEOM_PERIODIC = 2 };
 enum Far : int32_t { FAR_WALL = 0, FAR_EQ = 1 };
+enum Wall : int32_t { WALL_BB = 0, WALL_DS = 1 };
 
 // Per-step drive sample: wall velocity and lock-in basis at t_n = n + 1/2.
 struct Drive {
@@ -35,17 +36,18 @@ struct SolveState {
 };
 
 // Momentum exchange of the wall force, precomputed per solve on the host.
-// Population state: F += (wx, wy) * buf[off] for every bounce-back link
-// (off = the reflected population at the mirror cell).
+// Population state: F += (wx, wy) * buf[off] for every wall link (off = the
+// population at the mirror cell that crosses the wall), and M += wm * buf[off]
+// (the crossing mass, diffuse wall only).
 struct ForceLink {
   int64_t off;
-  double wx, wy;
+  double wx, wy, wm;
 };
-// Coefficient state: F += (wx . c, wy . c) per mirror cell, c_k = mbuf[k*mks + off]
-// (the cell's links folded into two 6-vectors).
+// Coefficient state: F += (wx . c, wy . c) and M += wm . c per mirror cell,
+// c_k = mbuf[k*mks + off] (the cell's links folded into 6-vectors).
 struct ForceCell {
   int64_t off;
-  double wx[6], wy[6];
+  double wx[6], wy[6], wm[6];
 };
 
 // Everything a kernel needs to advance one solve; lives in device memory.
@@ -76,6 +78,11 @@ struct SolveDesc {
   double ladd_scale;               // 2 rho0 / theta: moving-wall term per unit (w_i v_i.U)
   double fstatic[2];               // rest-state part of the wall force (geometry constant)
   double kladd[2];                 // force of the moving-wall terms per unit U_w
+  int32_t wall, pad3;              // WALL_BB or WALL_DS
+  // diffuse wall: A1 = sum_{vy>0} vy w, A2 = sum_{vy>0} vy w (vx^2/2th^2 - 1/2th),
+  // Bx = sum_{vy>0} vy vx^2 w / th, By0 = sum_{vy>0} vy^2 w,
+  // By2 = sum_{vy>0} vy^2 w (vx^2/2th^2 - 1/2th), nx rho0
+  double ds[6];
 };
 
 // One entry of the launch work list: a tile of one solve.

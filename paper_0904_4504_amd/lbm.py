@@ -17,7 +17,7 @@ OK, EINVAL, ENOMEM, EHIP, ERANGE, EUNSTABLE, EABI = 0, -1, -2, -3, -4, -5, -6
 D2Q9, D2Q37 = 9, 37
 STORE_F64, STORE_F32_DEV = 0, 1
 COLL_REGULARIZED, COLL_BGK = 0, 1
-WALL_BB = 0
+WALL_BB, WALL_DS = 0, 1
 GEOM_PLATE, GEOM_BOX, GEOM_PERIODIC = 0, 1, 2
 REPR_AUTO, REPR_POPULATIONS, REPR_COEFFICIENTS = 0, 1, 2
 FAR_WALL, FAR_EQ = 0, 1
@@ -141,6 +141,7 @@ def params_from_solve(s, history_capacity=0, tile=0, representation=REPR_AUTO):
     p.collision = COLL_REGULARIZED if s.collision == "regularized" else COLL_BGK
     p.geometry = {"plate": GEOM_PLATE, "box": GEOM_BOX, "periodic": GEOM_PERIODIC}[s.geometry]
     p.far = FAR_WALL if s.far == "wall" else FAR_EQ
+    p.wall = WALL_DS if getattr(s, "wall", "bb") == "ds" else WALL_BB
     p.nx, p.ny = s.nx, s.ny
     p.box_x0, p.box_y0, p.box_lx, p.box_ly = s.box
     p.tau, p.omega, p.u0, p.rho0 = s.tau, s.omega, s.u0, s.rho0

@@ -112,6 +112,8 @@ def _box(**kw):
     (_box, {"box_x0": 128 - 32 - 2}, B.EINVAL),
     (_box, {"representation": 3}, B.EINVAL),
     (_box, {"representation": B.REPR_COEFFICIENTS, "collision": B.COLL_BGK}, B.EINVAL),
+    (_box, {"wall": B.WALL_DS}, B.EINVAL),
+    (_plate, {"wall": 2}, B.EINVAL),
 ])
 def test_required_bytes_validation(make, kw, code):
     with pytest.raises(P.LbmError) as e:
@@ -134,6 +136,11 @@ def test_required_bytes_sizes():
     assert P.required_bytes(p) >= 2 * 37 * cells * 8
     p.tau = float("inf")
     P.required_bytes(p)
+
+
+def test_diffuse_wall_plate_is_accepted():
+    p = _plate(wall=B.WALL_DS)
+    assert P.required_bytes(p) == P.required_bytes(_plate())
 
 
 def test_beam_box_fits_one_gpu_with_room():

@@ -37,7 +37,8 @@ def _oracle_params(s, threads=0):
         geometry={W.PLATE: O.GEOM_PLATE, W.BOX: O.GEOM_BOX, W.PERIODIC: O.GEOM_PERIODIC}[s.geometry],
         far=O.FAR_WALL if s.far == W.FAR_WALL else O.FAR_EQ,
         collision=O.COLL_REGULARIZED if s.collision == "regularized" else O.COLL_BGK,
-        box_x0=s.box[0], box_y0=s.box[1], box_lx=s.box[2], box_ly=s.box[3], nthreads=threads)
+        box_x0=s.box[0], box_y0=s.box[1], box_lx=s.box[2], box_ly=s.box[3], nthreads=threads,
+        wall=O.WALL_DS if s.wall == "ds" else O.WALL_BB)
 
 
 def _gpu(P, s, f0=None, state=False, memory="torch", history_capacity=0, repr_=0, tile=0):
@@ -78,17 +79,18 @@ SMALL = {
 }
 
 
-def _small_solve(name, storage, nsteps=40):
+def _small_solve(name, storage, nsteps=40, wall="bb"):
     Q, geom, far, coll, nx, ny, box, tau = SMALL[name]
     om = 2 * math.pi / 32
     return W.Solve(Q=Q, geometry=geom, far=far, nx=nx, ny=ny, tau=tau, omega=om, u0=1e-3,
                    box=box, nsteps=nsteps, window_first=8, window_count=nsteps - 8,
-                   storage=storage, collision=coll, name=name)
+                   storage=storage, collision=coll, name=name, wall=wall)
 
 
-def _small_parity(P, name, storage, repr_, tile=0):
-    s = _small_solve(name, storage)
-    print(f"case {name} {storage} repr {repr_} tile {tile} {s.nx}x{s.ny}", flush=True)
+def _small_parity(P, name, storage, repr_, tile=0, wall="bb"):
+    s = _small_solve(name, storage, wall=wall)
+    print(f"case {name} {storage} repr {repr_} tile {tile} wall {wall} {s.nx}x{s.ny}",
+          flush=True)
     v, w, th = P.lattice(s.Q)
     f0 = _f0(s, w, seed=sum(map(ord, name)) % 1000, amp=1e-3)
     fx, fy, z, f = _gpu(P, s, f0, state=True, repr_=repr_, tile=tile)
@@ -126,6 +128,17 @@ def test_small_parity(P, name, storage, repr_):
     _small_parity(P, name, storage, repr_)
 
 
+@pytest.mark.parametrize("repr_", [1, 2], ids=["populations", "coefficients"])
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("name", ["q9_plate_wall_narrow", "q9_plate_eq_wide",
+                                  "q37_plate_wall_narrow", "q37_plate_eq_wide",
+                                  "q37_plate_large_tau"])
+def test_small_parity_diffuse_wall(P, name, storage, repr_):
+    """The diffuse-scattering moving wall (eq. DS) against the oracle:
+    populations after 40 steps, every per-step force and the impedance."""
+    _small_parity(P, name, storage, repr_, wall="ds")
+
+
 @pytest.mark.parametrize("tile", [1, 3])
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
 @pytest.mark.parametrize("name", ["q9_box", "q37_box", "q37_plate_eq_wide", "q37_periodic",
@@ -136,24 +149,36 @@ def test_small_parity_coef_tiles(P, name, storage, tile):
     _small_parity(P, name, storage, 2, tile)
 
 
+@pytest.mark.parametrize("wall", ["bb", "ds"])
 @pytest.mark.parametrize("Q", [9, 37])
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
-def test_first_step_and_free_molecular_limit(P, Q, storage):
-    """Closed forms: from rest F_0 = -2 rho0 U_w(1/2) nx C_s; with free
-    streaming (BGK, tau = inf) and an open far field F_n = -2 rho0 C_s nx U_w
-    at every step (eq. free-molecular, BB = 2 x DS)."""
+def test_first_step_and_free_molecular_limit(P, Q, storage, wall):
+    """Closed forms: with free streaming (BGK, tau = inf) and an open far
+    field every population reaching the wall is at rest (eq. free-molecular).
+    Bounce-back: F_n = -2 rho0 C_s nx U_w at every step.  Diffuse wall: the
+    wall emits w_i rho_w E_i(U_w) with rho_w = rho0 A1 / (A1 + U_w^2 A2), so
+    F_n = -rho0 C_s nx U_w A1 / (A1 + U_w^2 A2) -- half of bounce-back to
+    O(U_w^2) (BB = 2 x DS).  C_s = sum_{v_y<0} w |v_y| v_x^2 / theta,
+    A1 = sum_{v_y>0} v_y w, A2 = sum_{v_y>0} v_y w (v_x^2/2theta^2 - 1/2theta)."""
     v, w, th = P.lattice(Q)
     C_s = sum(w[i] * abs(v[i, 1]) * v[i, 0] ** 2 / th for i in range(Q) if v[i, 1] < 0)
+    A1 = sum(w[i] * v[i, 1] for i in range(Q) if v[i, 1] > 0)
+    A2 = sum(w[i] * v[i, 1] * (v[i, 0] ** 2 / (2 * th * th) - 1 / (2 * th))
+             for i in range(Q) if v[i, 1] > 0)
     om = 2 * math.pi / 64
     s = W.Solve(Q=Q, geometry=W.PLATE, far=W.FAR_EQ, nx=300, ny=40, tau=float("inf"),
                 omega=om, u0=1e-3, nsteps=256, window_first=64, window_count=192,
-                storage=storage, collision="bgk")
+                storage=storage, collision="bgk", wall=wall)
     fx, fy, z, _ = _gpu(P, s)
     U = 1e-3 * np.sin(om * (np.arange(256) + 0.5))
-    expect = -2 * C_s * s.nx * U
+    if wall == "bb":
+        expect = -2 * C_s * s.nx * U
+    else:
+        expect = -C_s * s.nx * U * A1 / (A1 + U * U * A2)
     tol = 1e-13 if storage == "f64" else 2e-7
     assert np.max(np.abs(fx - expect)) <= tol * np.max(np.abs(expect))
-    assert z["R"] / s.nx == pytest.approx(2 * C_s, rel=10 * tol)
+    R = (2 if wall == "bb" else 1) * C_s
+    assert z["R"] / s.nx == pytest.approx(R, rel=10 * tol if wall == "bb" else 1e-6)
     assert abs(z["X"] / s.nx) <= 10 * tol
 
 
