@@ -124,12 +124,15 @@ def sweep_mode(a):
     import torch
     import lbm_inputs as W
     import paper_0904_4504_amd as P
+    from paper_0904_4504_amd import autotune
     solves = [s.scaled(a.sweep_steps, a.sweep_steps // 2)
               for s in W.batch_sweep(count=a.sweep_solves)]
     cells = sum(s.fluid_cells for s in solves) * a.sweep_steps
     stream = torch.cuda.Stream()
     out = {}
     with torch.cuda.stream(stream):
+        # tile chosen by the autotuner on the largest solves of the sample
+        tile, tile_ms = autotune.tune(solves, stream=stream)
         # warm-up: one small solve through both paths (code objects, graphs)
         warm = solves[0].scaled(64, 32)
         with P.Solver(P.params_from_solve(warm), stream=stream) as sv:
@@ -137,7 +140,7 @@ def sweep_mode(a):
             sv.synchronize()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        solvers = [P.Solver(P.params_from_solve(s), stream=stream) for s in solves]
+        solvers = [P.Solver(P.params_from_solve(s, tile=tile), stream=stream) for s in solves]
         batch = P.Batch(stream)
         for sv in solvers:
             batch.add(sv)
@@ -151,7 +154,7 @@ def sweep_mode(a):
         t0 = time.perf_counter()
         zp = []
         for s in solves:
-            with P.Solver(P.params_from_solve(s), stream=stream) as sv:
+            with P.Solver(P.params_from_solve(s, tile=tile), stream=stream) as sv:
                 sv.step(a.sweep_steps)
                 sv.synchronize()
                 zp.append(sv.impedance())
@@ -166,7 +169,8 @@ def sweep_mode(a):
                                   f"256-solve draw (sides 256-2048, aspect 1/2/4, plate or box, "
                                   f"tau*omega 1e-2..1e2), {a.sweep_steps} steps each, D2Q37 FP32",
                       "wall_s_batched": tb, "wall_s_plain": tp,
-                      "solver_create_included": True}}
+                      "solver_create_included": True,
+                      "tile": tile, "autotune_ms_per_step": tile_ms}}
     print(json.dumps(out), flush=True)
 
 

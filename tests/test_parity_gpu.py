@@ -506,3 +506,18 @@ def test_tile_variants_agree(P, name, storage, repr_):
             ferr = np.max(np.abs(fx - out[0][0])) / np.max(np.abs(out[0][0]))
             print(f"coefficient tiles {name} {storage}: state {err:.2e} force {ferr:.2e}", flush=True)
             assert err <= tol and ferr <= tol
+
+
+def test_autotune_picks_a_tile_of_the_representation(P):
+    """The autotuner times every tile of the representation the solves use
+    and returns the fastest; a solver built with it matches the default."""
+    from paper_0904_4504_amd import autotune
+    solves = [_small_solve(n, "f32dev", nsteps=40) for n in ("q37_box", "q37_plate_eq_wide")]
+    tile, times = autotune.tune(solves, steps=8, warmup=2, use_cache=False)
+    assert sorted(times) == [1, 2, 3] and tile == min(times, key=times.get)
+    out = []
+    for t in (0, tile):
+        with P.Solver(P.params_from_solve(solves[0], tile=t)) as sv:
+            sv.step(solves[0].nsteps)
+            out.append(sv.force_history(0, solves[0].nsteps)[0])
+    assert np.max(np.abs(out[1] - out[0])) <= 2e-6 * np.max(np.abs(out[0]))
