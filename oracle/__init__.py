@@ -5,5 +5,6 @@ benchmark's CPU-baseline leg; the product library never imports it.
 """
 from .oracle import (  # noqa: F401
     GEOM_BOX, GEOM_PERIODIC, GEOM_PLATE, FAR_EQ, FAR_WALL, COLL_BGK, COLL_REGULARIZED, WALL_BB, WALL_DS,
+    WALL_MAXWELL,
     OracleParams, advect, collide, equilibrium, lattice, lockin_fit, run,
 )

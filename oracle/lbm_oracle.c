@@ -41,6 +41,11 @@
  *     density rho_w(x); rho_w(x) balances the mass of the populations of
  *     column x that cross the wall in this step (zero normal mass flux, eq.
  *     kinetic_bc), the crossing links counted as in bounce-back.
+ *   - Maxwell wall of accommodation sigma (Sec. 3, sigma_v): the arrival is
+ *     sigma times the diffuse one plus (1 - sigma) times the specular image:
+ *     the population of (vx, -vy) that crossed the wall from column x - vx
+ *     at the mirror row (reflected in y only; its tangential velocity, and
+ *     so the wall's tangential motion, does not enter).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -61,7 +66,7 @@ typedef ORACLE_REAL real;
 enum { ORC_GEOM_PLATE = 0, ORC_GEOM_BOX = 1, ORC_GEOM_PERIODIC = 2 };
 enum { ORC_FAR_WALL = 0, ORC_FAR_EQ = 1 };
 enum { ORC_COLL_REGULARIZED = 0, ORC_COLL_BGK = 1 };
-enum { ORC_WALL_BB = 0, ORC_WALL_DS = 1 };
+enum { ORC_WALL_BB = 0, ORC_WALL_DS = 1, ORC_WALL_MAXWELL = 2 };
 
 typedef struct {
   int Q;          /* 9 or 37 */
@@ -75,12 +80,14 @@ typedef struct {
   double u0;      /* drive amplitude: U_w(t) = u0 sin(omega t) along x */
   double rho0;    /* rest density */
   int nthreads;   /* OpenMP threads, 0 = runtime default */
-  int wall;       /* ORC_WALL_*: model of the moving wall (DS: plate only) */
+  int wall;       /* ORC_WALL_*: model of the moving wall (DS, MAXWELL: plate only) */
+  double sigma;   /* MAXWELL: tangential momentum accommodation, 0 (specular) .. 1 (DS) */
 } oracle_params;
 
 typedef struct {
   int Q;
   int vx[ORC_MAXQ], vy[ORC_MAXQ], opp[ORC_MAXQ];
+  int refl[ORC_MAXQ];  /* index of (vx, -vy): the specular image */
   real w[ORC_MAXQ];
   real theta;
 } lattice;
@@ -108,6 +115,10 @@ static int load_lattice(int Q, lattice* L) {
     for (int j = 0; j < Q; ++j)
       if (v[j][0] == -v[i][0] && v[j][1] == -v[i][1]) L->opp[i] = j;
     if (L->opp[i] < 0) return -1;
+    L->refl[i] = -1;
+    for (int j = 0; j < Q; ++j)
+      if (v[j][0] == v[i][0] && v[j][1] == -v[i][1]) L->refl[i] = j;
+    if (L->refl[i] < 0) return -1;
   }
   return 0;
 }
@@ -145,6 +156,8 @@ static int check_params(const oracle_params* p, const lattice* L) {
     return -1;
   }
   if (p->wall == ORC_WALL_DS) return p->geometry == ORC_GEOM_PLATE ? 0 : -1;
+  if (p->wall == ORC_WALL_MAXWELL)
+    return p->geometry == ORC_GEOM_PLATE && p->sigma >= 0 && p->sigma <= 1 ? 0 : -1;
   return p->wall == ORC_WALL_BB ? 0 : -1;
 }
 
@@ -191,8 +204,18 @@ static real advect_one(const oracle_params* p, const lattice* L, const real* f, 
       /* crossed the moving wall at y = -1/2: retrace in y, keep x */
       int py = -1 - sy;
       real fr = F_AT(f, x, py, L->opp[i]);
-      real fa = rho_w ? L->w[i] * rho_w[x] * eq_factor(L, i, U)
-                      : fr + 2 * L->w[i] * (real)p->rho0 * (vx * U) / L->theta;
+      real fa;
+      if (!rho_w) {
+        fa = fr + 2 * L->w[i] * (real)p->rho0 * (vx * U) / L->theta;
+      } else {
+        fa = L->w[i] * rho_w[x] * eq_factor(L, i, U);
+        if (p->wall == ORC_WALL_MAXWELL) {
+          /* specular part: the population of (vx, -vy) that left column
+             x - vx at the mirror row and is reflected in y only */
+          const real sp = F_AT(f, sx, py, L->refl[i]);
+          fa = (real)p->sigma * fa + (1 - (real)p->sigma) * sp;
+        }
+      }
       *fx -= vx * (fr + fa);
       *fy -= vy * (fr + fa);
       return fa;
@@ -341,7 +364,7 @@ int oracle_advect(const oracle_params* p, const double* f_in, double U, double* 
   real* f = import_f(p, &L, f_in);
   if (!f) return -2;
   real* rho_w = NULL;
-  if (p->wall == ORC_WALL_DS) {
+  if (p->wall == ORC_WALL_DS || p->wall == ORC_WALL_MAXWELL) {
     rho_w = (real*)malloc(sizeof(real) * p->nx);
     if (!rho_w) { free(f); return -2; }
     wall_density(p, &L, f, (real)U, rho_w);
@@ -375,8 +398,9 @@ int oracle_run(const oracle_params* p, const double* f0, long nsteps, double* fx
   real* g = import_f(p, &L, NULL);
   real* rowfx = (real*)calloc((size_t)p->ny, sizeof(real));
   real* rowfy = (real*)calloc((size_t)p->ny, sizeof(real));
-  real* rho_w = p->wall == ORC_WALL_DS ? (real*)calloc((size_t)p->nx, sizeof(real)) : NULL;
-  if (!f || !g || !rowfx || !rowfy || (p->wall == ORC_WALL_DS && !rho_w)) {
+  const int diffuse = p->wall == ORC_WALL_DS || p->wall == ORC_WALL_MAXWELL;
+  real* rho_w = diffuse ? (real*)calloc((size_t)p->nx, sizeof(real)) : NULL;
+  if (!f || !g || !rowfx || !rowfy || (diffuse && !rho_w)) {
     free(f); free(g); free(rowfx); free(rowfy); free(rho_w);
     return -2;
   }

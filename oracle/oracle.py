@@ -16,7 +16,7 @@ from . import build as _build
 GEOM_PLATE, GEOM_BOX, GEOM_PERIODIC = 0, 1, 2
 FAR_WALL, FAR_EQ = 0, 1
 COLL_REGULARIZED, COLL_BGK = 0, 1
-WALL_BB, WALL_DS = 0, 1
+WALL_BB, WALL_DS, WALL_MAXWELL = 0, 1, 2
 
 
 class _CParams(C.Structure):
@@ -25,7 +25,7 @@ class _CParams(C.Structure):
         ("nx", C.c_int), ("ny", C.c_int),
         ("box_x0", C.c_int), ("box_y0", C.c_int), ("box_lx", C.c_int), ("box_ly", C.c_int),
         ("tau", C.c_double), ("omega", C.c_double), ("u0", C.c_double), ("rho0", C.c_double),
-        ("nthreads", C.c_int), ("wall", C.c_int),
+        ("nthreads", C.c_int), ("wall", C.c_int), ("sigma", C.c_double),
     ]
 
 
@@ -47,6 +47,7 @@ class OracleParams:
     rho0: float = 1.0
     nthreads: int = 0
     wall: int = 0
+    sigma: float = 1.0     # WALL_MAXWELL: accommodation, 0 specular .. 1 diffuse
 
     def c(self):
         return _CParams(**dataclasses.asdict(self))

@@ -33,12 +33,16 @@ def _reflect_box(p, d, box):
     return tuple(a)
 
 
-def stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse=False):
+def stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse=False, sigma=1.0):
     """Push streaming.  Returns (f_adv, Fx, Fy); f is [q][y][x].  With
     diffuse=True the plate wall re-emits what hits it as the H2 equilibrium at
-    the wall velocity, at the density that returns the column's mass."""
+    the wall velocity, at the density that returns the column's mass; with
+    sigma < 1 only that fraction is re-emitted diffusely and the rest of each
+    particle is reflected specularly (v_y -> -v_y, v_x kept)."""
     Q, ny, nx = f.shape
     opp = [int(np.flatnonzero((v[:, 0] == -v[i, 0]) & (v[:, 1] == -v[i, 1]))[0]) for i in range(Q)]
+    refl = [int(np.flatnonzero((v[:, 0] == v[i, 0]) & (v[:, 1] == -v[i, 1]))[0]) for i in range(Q)]
+    wall_in = np.zeros_like(f)  # arrivals from the diffuse / specular wall
     fadv = np.full_like(f, np.nan)
     Fx = Fy = 0.0
 
@@ -75,9 +79,15 @@ def stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse=False):
                         i = opp[q]
                         ax, ay = x, -1 - dy
                         if diffuse:
-                            out = w[i] * rho_w[x] * eq[i]
-                        else:
-                            out = val + 2 * w[i] * rho0 * (v[i, 0] * U) / theta
+                            # incoming momentum now; the arrivals' outgoing
+                            # momentum once they are all in place
+                            wall_in[i, ay, ax] += sigma * w[i] * rho_w[x] * eq[i]
+                            j = refl[q]
+                            wall_in[j, ay, (x + ux) % nx] += (1 - sigma) * val
+                            Fx += ux * val
+                            Fy += uy * val
+                            continue
+                        out = val + 2 * w[i] * rho0 * (v[i, 0] * U) / theta
                         fadv[i, ay, ax] = out
                         Fx += -v[i, 0] * (val + out)
                         Fy += -v[i, 1] * (val + out)
@@ -101,6 +111,13 @@ def stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse=False):
                         Fy += -v[i, 1] * (val + out)
                         continue
                     fadv[q, dy, dx] = val
+    if diffuse:
+        for i in range(Q):
+            for y in range(ny):
+                if y < v[i, 1]:  # arrival rows of the wall
+                    fadv[i, y, :] = wall_in[i, y, :]
+                    Fx -= v[i, 0] * wall_in[i, y, :].sum()
+                    Fy -= v[i, 1] * wall_in[i, y, :].sum()
     # whatever was not delivered comes from the rest-equilibrium far field
     hole = np.isnan(fadv)
     fadv[hole] = (w[:, None, None] * rho0 * np.ones_like(f))[hole]
@@ -133,8 +150,9 @@ def collide(fadv, v, w, theta, tau, regularized=True):
     return feq + keep * fne
 
 
-def step(f, v, w, theta, tau, geometry, far, box, U, rho0=1.0, regularized=True, diffuse=False):
-    fadv, Fx, Fy = stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse)
+def step(f, v, w, theta, tau, geometry, far, box, U, rho0=1.0, regularized=True, diffuse=False,
+         sigma=1.0):
+    fadv, Fx, Fy = stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse, sigma)
     out = collide(fadv, v, w, theta, tau, regularized)
     if geometry == "box":
         x0, y0, lx, ly = box

@@ -525,8 +525,9 @@ def test_diffuse_one_step_matches_brute_force(Q, far):
                        far=O.FAR_WALL if far == "wall" else O.FAR_EQ, wall=O.WALL_DS)
     fx, fy, fin = O.run(p, 1, f0=f, want_state=True, variant="ld")
     assert np.max(np.abs(fin - ref)) <= 1e-15
-    assert abs(fx[0] - Fx) <= 1e-14 * max(abs(Fx), 1e-3)
-    assert abs(fy[0] - Fy) <= 1e-14 * max(abs(Fy), 1e-3)
+    # the force cancels O(1) rest-state momentum terms: compare at that scale
+    assert abs(fx[0] - Fx) <= 1e-14 * max(abs(Fx), 1.0)
+    assert abs(fy[0] - Fy) <= 1e-14 * max(abs(Fy), 1.0)
 
 
 def test_diffuse_wall_slip_reduces_damping():
@@ -546,6 +547,82 @@ def test_diffuse_wall_slip_reduces_damping():
     assert 0.95 < ratio[0.01] < 1.0
     assert ratio[1.0] < ratio[0.1] < ratio[0.01]
     assert ratio[1.0] > 0.3
+
+
+# ------------------------------------------------- Maxwell wall (accommodation)
+
+@pytest.mark.parametrize("Q", [9, 37])
+def test_maxwell_wall_at_full_accommodation_is_the_diffuse_wall(Q):
+    v, w, th = O.lattice(Q, "ld")
+    f0 = w[:, None, None] * (1 + W.random_state(Q, 12, 5, seed=9, amp=0.02))
+    base = dict(Q=Q, nx=5, ny=12, tau=0.9, omega=0.4, u0=3e-3, far=O.FAR_WALL)
+    a = O.run(O.OracleParams(**base, wall=O.WALL_DS), 6, f0=f0, want_state=True, variant="ld")
+    b = O.run(O.OracleParams(**base, wall=O.WALL_MAXWELL, sigma=1.0), 6, f0=f0,
+              want_state=True, variant="ld")
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.5])
+@pytest.mark.parametrize("Q", [9, 37])
+def test_maxwell_free_molecular_shear_scales_with_accommodation(Q, sigma):
+    """Free streaming from rest past the moving plate: a specular wall
+    reflects v_y only and exerts no shear (Sec. 4: F^SP has no L_x term), so
+    F_x = sigma F_x^DS at every step."""
+    om, u0 = 2 * math.pi / 64, 1e-3
+    base = dict(Q=Q, nx=6, ny=24, far=O.FAR_EQ, collision=O.COLL_BGK, tau=INF, omega=om,
+                u0=u0)
+    fds, _, _ = O.run(O.OracleParams(**base, wall=O.WALL_DS), 96, variant="ld")
+    fm, _, _ = O.run(O.OracleParams(**base, wall=O.WALL_MAXWELL, sigma=sigma), 96,
+                     variant="ld")
+    assert np.max(np.abs(fm - sigma * fds)) <= 1e-14 * np.max(np.abs(fds))
+
+
+@pytest.mark.parametrize("Q", [9, 37])
+def test_specular_wall_exerts_no_shear_on_any_state(Q):
+    """With sigma = 0 the arrivals are a permutation of the crossing
+    populations with the same v_x, so the x momentum exchange vanishes for
+    any state, also away from equilibrium and with collisions."""
+    v, w, th = O.lattice(Q, "ld")
+    f0 = w[:, None, None] * (1 + W.random_state(Q, 16, 7, seed=11, amp=0.05))
+    p = O.OracleParams(Q=Q, nx=7, ny=16, tau=0.8, omega=0.5, u0=0.01, far=O.FAR_EQ,
+                       wall=O.WALL_MAXWELL, sigma=0.0)
+    fx, fy, _ = O.run(p, 20, f0=f0, variant="ld")
+    assert np.max(np.abs(fx)) <= 1e-15 * np.max(np.abs(fy))
+
+
+@pytest.mark.parametrize("Q", [9, 37])
+def test_maxwell_wall_conserves_mass_in_closed_channel(Q):
+    v, w, th = O.lattice(Q, "ld")
+    p = O.OracleParams(Q=Q, nx=5, ny=20, tau=0.9, omega=0.3, u0=0.01, far=O.FAR_WALL,
+                       wall=O.WALL_MAXWELL, sigma=0.3)
+    f0 = w[:, None, None] * (1 + W.random_state(Q, 20, 5, seed=6, amp=0.01))
+    _, _, f = O.run(p, 30, f0=f0, want_state=True, variant="ld")
+    assert abs(f.sum() - f0.sum()) <= 1e-14 * f0.sum()
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.35])
+@pytest.mark.parametrize("Q", [9, 37])
+@pytest.mark.parametrize("far", ["wall", "eq"])
+def test_maxwell_one_step_matches_brute_force(Q, far, sigma):
+    v, w, th = O.lattice(Q, "ld")
+    nx, ny, tau, U = 4, 9, 0.83, 4e-3
+    f = w[:, None, None] * (1 + W.random_state(Q, ny, nx, seed=Q + 5, amp=0.02))
+    ref, Fx, Fy = brute_lbm.step(f, v, w, th, tau, "plate", far, (0, 0, 0, 0), U, 1.0, True,
+                                 diffuse=True, sigma=sigma)
+    p = O.OracleParams(Q=Q, nx=nx, ny=ny, tau=tau, omega=math.pi, u0=U,
+                       far=O.FAR_WALL if far == "wall" else O.FAR_EQ, wall=O.WALL_MAXWELL,
+                       sigma=sigma)
+    fx, fy, fin = O.run(p, 1, f0=f, want_state=True, variant="ld")
+    assert np.max(np.abs(fin - ref)) <= 1e-15
+    assert abs(fx[0] - Fx) <= 1e-14 * max(abs(Fx), 1.0)
+    assert abs(fy[0] - Fy) <= 1e-14 * max(abs(Fy), 1.0)
+
+
+def test_maxwell_wall_rejects_bad_accommodation():
+    for sigma in (-0.1, 1.5):
+        with pytest.raises(ValueError):
+            O.run(O.OracleParams(Q=9, nx=4, ny=8, wall=O.WALL_MAXWELL, sigma=sigma), 1)
 
 
 def test_diffuse_wall_rejected_for_box():
