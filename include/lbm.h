@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 typedef struct lbm_solver lbm_solver; /* opaque; owned by the library */
 
@@ -74,8 +74,13 @@ enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
  * velocity with the wall density rho_w(x) that balances the mass of the
  * populations of column x crossing the wall in that step (zero normal mass
  * flux, eq. kinetic_bc; the crossing populations are those bounce-back
- * would reflect into column x).  The stationary far wall stays bounce-back. */
-enum { LBM_WALL_BB = 0, LBM_WALL_DS = 1 };
+ * would reflect into column x).  Maxwell wall (plate only): a fraction
+ * `accommodation` (sigma_v of Sec. 3, 0..1) of every arrival is the diffuse
+ * one and the rest the specular image -- the population of (vx, -vy) that
+ * crossed the wall from column x - vx at the mirror row, reflected in y
+ * only; 1 is the diffuse wall, 0 specular reflection (no shear).  The
+ * stationary far wall stays bounce-back. */
+enum { LBM_WALL_BB = 0, LBM_WALL_DS = 1, LBM_WALL_MAXWELL = 2 };
 
 /* Geometry.
  *  PLATE:    x periodic (nx cells); the moving wall lies half-way below row
@@ -104,7 +109,7 @@ typedef struct lbm_params {
   uint32_t lattice;      /* LBM_D2Q9 or LBM_D2Q37 */
   uint32_t storage;      /* LBM_STORE_* */
   uint32_t collision;    /* LBM_COLL_* */
-  uint32_t wall;         /* LBM_WALL_BB or LBM_WALL_DS (plate only) */
+  uint32_t wall;         /* LBM_WALL_BB, or LBM_WALL_DS / LBM_WALL_MAXWELL (plate only) */
   uint32_t geometry;     /* LBM_GEOM_* */
   uint32_t far;          /* LBM_FAR_* */
   uint32_t tile;         /* kernel tile.  Populations: 0 (= 1), 1, 2 or 4; one workgroup of
@@ -128,10 +133,12 @@ typedef struct lbm_params {
   int64_t lockin_first;  /* lock-in window [first, first + count) in steps */
   int64_t lockin_count;
   int64_t history_capacity; /* force samples kept on the device (ring); 0 = max_steps */
+  double accommodation;  /* LBM_WALL_MAXWELL: fraction of diffuse re-emission, 0..1 */
 } lbm_params;
 
 /* Fill *p with defaults: ABI version, D2Q37, F32_DEV, regularized, BB, plate
- * with a stationary far wall, rho0 = 1; sizes, tau, drive and steps zero. */
+ * with a stationary far wall, rho0 = 1, accommodation 1; sizes, tau, drive
+ * and steps zero. */
 int lbm_params_init(lbm_params* p);
 
 /* Velocity set in canonical order (orbits of the appendix table, members by

@@ -54,7 +54,8 @@ class Solve:
     window_count: int = 0
     storage: str = "f32dev"    # "f64" or "f32dev"
     collision: str = "regularized"
-    wall: str = "bb"           # model of the moving wall: "bb" or "ds" (plate only)
+    wall: str = "bb"           # moving wall: "bb", or "ds" / "maxwell" (plate only)
+    accommodation: float = 1.0  # "maxwell": fraction re-emitted diffusely (0 specular)
     noise: float = 0.0
     seed: int = 0
     tau_omega: float = float("nan")

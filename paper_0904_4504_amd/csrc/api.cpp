@@ -85,8 +85,11 @@ int validate(const lbm_params* p, HostLattice* lat) {
   if (!host_lattice((int)p->lattice, lat)) return LBM_EINVAL;
   if (p->storage != LBM_STORE_F64 && p->storage != LBM_STORE_F32_DEV) return LBM_EINVAL;
   if (p->collision != LBM_COLL_REGULARIZED && p->collision != LBM_COLL_BGK) return LBM_EINVAL;
-  if (p->wall != LBM_WALL_BB && p->wall != LBM_WALL_DS) return LBM_EINVAL;
-  if (p->wall == LBM_WALL_DS && p->geometry != LBM_GEOM_PLATE) return LBM_EINVAL;
+  if (p->wall != LBM_WALL_BB && p->wall != LBM_WALL_DS && p->wall != LBM_WALL_MAXWELL)
+    return LBM_EINVAL;
+  if (p->wall != LBM_WALL_BB && p->geometry != LBM_GEOM_PLATE) return LBM_EINVAL;
+  if (p->wall == LBM_WALL_MAXWELL && !(p->accommodation >= 0.0 && p->accommodation <= 1.0))
+    return LBM_EINVAL;
   if (p->far != LBM_FAR_WALL && p->far != LBM_FAR_EQ) return LBM_EINVAL;
   if (p->representation > LBM_REPR_COEFFICIENTS) return LBM_EINVAL;
   if (p->representation == LBM_REPR_COEFFICIENTS && p->collision != LBM_COLL_REGULARIZED)
@@ -178,8 +181,13 @@ struct ForceTables {
 void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout& lay,
                         ForceTables* t) {
   long double sx = 0, sy = 0, kx = 0, ky = 0;
-  const bool diffuse = p->wall == LBM_WALL_DS;
-  const long double mw = diffuse ? 1.0L : 2.0L;  // weight of the reflected deviation
+  // diffuse or Maxwell wall: a share sigma of every arrival is the diffuse
+  // emission, the rest the specular image of a crossing population (the
+  // same v_x): shear sees sigma of the reflected deviations, the normal
+  // force 2 - sigma of them
+  const bool diffuse = p->wall == LBM_WALL_DS || p->wall == LBM_WALL_MAXWELL;
+  const long double sigma = p->wall == LBM_WALL_MAXWELL ? (long double)p->accommodation : 1.0L;
+  const long double mwx = diffuse ? sigma : 2.0L, mwy = diffuse ? 2.0L - sigma : 2.0L;
   std::unordered_map<int64_t, size_t> index;  // mirror cell -> position in t->cells
   auto cell_for = [&](int px, int py) -> ForceCell& {
     const int64_t key = (int64_t)py * p->nx + px;
@@ -213,8 +221,8 @@ void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout&
         }
         int px, py;
         mirror_of(p, L, x, y, q, &px, &py);
-        t->links.push_back(ForceLink{L.opp[q] * lay.qs + py * lay.ys + px, (double)(-mw * vx),
-                                     (double)(-mw * vy), diffuse ? 1.0 : 0.0});
+        t->links.push_back(ForceLink{L.opp[q] * lay.qs + py * lay.ys + px, (double)(-mwx * vx),
+                                     (double)(-mwy * vy), diffuse ? 1.0 : 0.0});
         if (lay.mom) {
           ForceCell& fc = cell_for(px, py);
           // basis of the opposite direction -v at the mirror cell
@@ -222,8 +230,8 @@ void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout&
                                     (long double)vx * vx, (long double)vx * vy,
                                     (long double)vy * vy};
           for (int k = 0; k < 6; ++k) {
-            fc.wx[k] += (double)(-mw * vx * w * g[k]);
-            fc.wy[k] += (double)(-mw * vy * w * g[k]);
+            fc.wx[k] += (double)(-mwx * vx * w * g[k]);
+            fc.wy[k] += (double)(-mwy * vy * w * g[k]);
             if (diffuse) fc.wm[k] += (double)(w * g[k]);
           }
         }
@@ -382,7 +390,8 @@ int init_solver(lbm_solver* s) {
   d.fstatic[1] = ft.fstatic[1];
   d.kladd[0] = ft.kladd[0];
   d.kladd[1] = ft.kladd[1];
-  d.wall = p->wall == LBM_WALL_DS ? WALL_DS : WALL_BB;
+  d.wall = p->wall == LBM_WALL_BB ? WALL_BB : WALL_DS;
+  d.sigma = p->wall == LBM_WALL_MAXWELL ? p->accommodation : 1.0;
   for (int k = 0; k < 6; ++k) d.ds[k] = ft.ds[k];
   if (lay.mom) {
     d.mbuf[0] = b + lay.off_mbuf[0];
@@ -513,7 +522,7 @@ int step_one(lbm_solver* s) {
                     s->stream);
     s->pop_pending = false;
   } else {
-    e = launch_coef(Q, f64, s->lay.coef_k, s->p.wall == LBM_WALL_DS, s->d_desc, s->d_mwork,
+    e = launch_coef(Q, f64, s->lay.coef_k, s->p.wall != LBM_WALL_BB, s->d_desc, s->d_mwork,
                     s->lay.mnwork, s->klat, s->stream);
     mode = 1;
   }
@@ -550,6 +559,7 @@ int lbm_params_init(lbm_params* p) {
   p->storage = LBM_STORE_F32_DEV;
   p->collision = LBM_COLL_REGULARIZED;
   p->wall = LBM_WALL_BB;
+  p->accommodation = 1.0;
   p->geometry = LBM_GEOM_PLATE;
   p->far = LBM_FAR_WALL;
   p->rho0 = 1.0;

@@ -80,7 +80,7 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
   std::vector<int32_t> solves;
   b->any_ds = false;
   for (size_t i = 0; i < act.size(); ++i) {
-    if (act[i]->lay.mom && act[i]->p.wall == LBM_WALL_DS) b->any_ds = true;
+    if (act[i]->lay.mom && act[i]->p.wall != LBM_WALL_BB) b->any_ds = true;
     descs.push_back(act[i]->desc);
     solves.push_back((int32_t)i);
     const Layout& lay = act[i]->lay;

@@ -164,7 +164,22 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<c
       const S wq = (S)lat.w[L::orbit[q]];
       S f;
       if (DSW && diffuse) {
-        f = (S)ds_arrival<vx>(d, U, cm, lat.w[L::orbit[q]], lat.theta);
+        double e = ds_arrival<vx>(d, U, cm, lat.w[L::orbit[q]], lat.theta);
+        if (d.sigma != 1.0) {
+          // specular share: the population of (vx, -vy) that crossed the
+          // wall from column x - vx at the mirror row
+          int sxw = x - vx;
+          sxw += sxw < 0 ? d.nx : 0;
+          sxw -= sxw >= d.nx ? d.nx : 0;
+          const int g = py * ys + sxw;
+          double p = min[g];
+          if constexpr (vx != 0) p += double(vx) * min[ks + g] + double(vx * vx) * min[3 * ks + g];
+          if constexpr (vy != 0)
+            p += double(-vy) * min[2 * ks + g] + double(vy * vy) * min[5 * ks + g];
+          if constexpr (vx * vy != 0) p += double(-vx * vy) * min[4 * ks + g];
+          e = d.sigma * e + (1.0 - d.sigma) * lat.w[L::orbit[q]] * p;
+        }
+        f = (S)e;
       } else {
         const int g = py * ys + px;
         // population of -v at the mirror cell

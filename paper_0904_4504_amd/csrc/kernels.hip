@@ -65,10 +65,17 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
     sx -= sx >= nx ? nx : 0;
     if constexpr (vy > 0) {
       if (sy < 0) {
-        // from the moving wall at y = -1/2: diffuse emission, or bounce-back
-        // (retrace in y, keep x)
-        if (d.wall == WALL_DS) return (S)ds_arrival<vx>(d, U, cm, wq, theta);
+        // from the moving wall at y = -1/2: diffuse emission (a share sigma;
+        // the rest the specular image, the population of (vx, -vy) from
+        // column x - vx at the mirror row), or bounce-back (retrace in y,
+        // keep x)
         const int py = -1 - sy;
+        if (d.wall == WALL_DS) {
+          const double e = ds_arrival<vx>(d, U, cm, wq, theta);
+          if (d.sigma == 1.0) return (S)e;
+          constexpr int qr = reflect_y<L>(q);
+          return (S)(d.sigma * e + (1.0 - d.sigma) * (double)fin[qr * qs + py * ys + sx]);
+        }
         return fin[o * qs + py * ys + x] + (S)(wq * vx * ladd);
       }
     }
@@ -302,8 +309,9 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
       const double U = dr.u, uu = U * U;
       const double emit = d.ds[0] + uu * d.ds[1];
       const double nr = d.ds[5];
-      fx -= (nr * d.ds[0] * U * d.ds[2] + sm * U * d.ds[2]) / emit;
-      fy -= (nr * uu * (d.ds[0] * d.ds[4] - d.ds[1] * d.ds[3]) + sm * (d.ds[3] + uu * d.ds[4])) /
+      fx -= d.sigma * (nr * d.ds[0] * U * d.ds[2] + sm * U * d.ds[2]) / emit;
+      fy -= d.sigma *
+            (nr * uu * (d.ds[0] * d.ds[4] - d.ds[1] * d.ds[3]) + sm * (d.ds[3] + uu * d.ds[4])) /
             emit;
     }
     const int64_t h = n % d.hist_cap;

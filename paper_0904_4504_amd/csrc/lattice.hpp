@@ -53,6 +53,14 @@ constexpr int opposite(int i) {
   return -1;
 }
 
+// Index of the specular image (vx, -vy), evaluated at compile time.
+template <class L>
+constexpr int reflect_y(int i) {
+  for (int j = 0; j < L::Q; ++j)
+    if (L::vx[j] == L::vx[i] && L::vy[j] == -L::vy[i]) return j;
+  return -1;
+}
+
 // Quadrature weights per orbit and theta, derived on the host.
 struct LatticeWeights {
   int Q;

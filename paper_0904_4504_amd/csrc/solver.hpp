@@ -78,7 +78,8 @@ struct SolveDesc {
   double ladd_scale;               // 2 rho0 / theta: moving-wall term per unit (w_i v_i.U)
   double fstatic[2];               // rest-state part of the wall force (geometry constant)
   double kladd[2];                 // force of the moving-wall terms per unit U_w
-  int32_t wall, pad3;              // WALL_BB or WALL_DS
+  int32_t wall, pad3;              // WALL_BB or WALL_DS (diffuse share sigma, rest specular)
+  double sigma;                    // accommodation: 1 diffuse .. 0 specular
   // diffuse wall: A1 = sum_{vy>0} vy w, A2 = sum_{vy>0} vy w (vx^2/2th^2 - 1/2th),
   // Bx = sum_{vy>0} vy vx^2 w / th, By0 = sum_{vy>0} vy^2 w,
   // By2 = sum_{vy>0} vy^2 w (vx^2/2th^2 - 1/2th), nx rho0

@@ -12,12 +12,12 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, ENOMEM, EHIP, ERANGE, EUNSTABLE, EABI = 0, -1, -2, -3, -4, -5, -6
 D2Q9, D2Q37 = 9, 37
 STORE_F64, STORE_F32_DEV = 0, 1
 COLL_REGULARIZED, COLL_BGK = 0, 1
-WALL_BB, WALL_DS = 0, 1
+WALL_BB, WALL_DS, WALL_MAXWELL = 0, 1, 2
 GEOM_PLATE, GEOM_BOX, GEOM_PERIODIC = 0, 1, 2
 REPR_AUTO, REPR_POPULATIONS, REPR_COEFFICIENTS = 0, 1, 2
 FAR_WALL, FAR_EQ = 0, 1
@@ -50,7 +50,7 @@ class Params(C.Structure):
         ("box_ly", C.c_int32), ("tau", C.c_double), ("omega", C.c_double),
         ("u0", C.c_double), ("rho0", C.c_double), ("max_steps", C.c_int64),
         ("lockin_first", C.c_int64), ("lockin_count", C.c_int64),
-        ("history_capacity", C.c_int64),
+        ("history_capacity", C.c_int64), ("accommodation", C.c_double),
     ]
 
 
@@ -141,7 +141,8 @@ def params_from_solve(s, history_capacity=0, tile=0, representation=REPR_AUTO):
     p.collision = COLL_REGULARIZED if s.collision == "regularized" else COLL_BGK
     p.geometry = {"plate": GEOM_PLATE, "box": GEOM_BOX, "periodic": GEOM_PERIODIC}[s.geometry]
     p.far = FAR_WALL if s.far == "wall" else FAR_EQ
-    p.wall = WALL_DS if getattr(s, "wall", "bb") == "ds" else WALL_BB
+    p.wall = {"bb": WALL_BB, "ds": WALL_DS, "maxwell": WALL_MAXWELL}[getattr(s, "wall", "bb")]
+    p.accommodation = getattr(s, "accommodation", 1.0)
     p.nx, p.ny = s.nx, s.ny
     p.box_x0, p.box_y0, p.box_lx, p.box_ly = s.box
     p.tau, p.omega, p.u0, p.rho0 = s.tau, s.omega, s.u0, s.rho0

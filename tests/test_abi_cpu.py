@@ -47,9 +47,9 @@ def test_header_is_plain_c_and_struct_layout_matches_binding():
 #include <stddef.h>
 #include "lbm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(lbm_params), offsetof(lbm_params, tau),
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lbm_params), offsetof(lbm_params, tau),
          offsetof(lbm_params, max_steps), offsetof(lbm_params, history_capacity),
-         offsetof(lbm_params, box_ly));
+         offsetof(lbm_params, box_ly), offsetof(lbm_params, accommodation));
   return 0;
 }
 """
@@ -62,7 +62,8 @@ int main(void) {
         got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
                                               check=True).stdout.split()]
     expect = [C.sizeof(B.Params), B.Params.tau.offset, B.Params.max_steps.offset,
-              B.Params.history_capacity.offset, B.Params.box_ly.offset]
+              B.Params.history_capacity.offset, B.Params.box_ly.offset,
+              B.Params.accommodation.offset]
     assert got == expect
 
 
@@ -113,7 +114,12 @@ def _box(**kw):
     (_box, {"representation": 3}, B.EINVAL),
     (_box, {"representation": B.REPR_COEFFICIENTS, "collision": B.COLL_BGK}, B.EINVAL),
     (_box, {"wall": B.WALL_DS}, B.EINVAL),
-    (_plate, {"wall": 2}, B.EINVAL),
+    (_box, {"wall": B.WALL_MAXWELL, "accommodation": 0.5}, B.EINVAL),
+    (_plate, {"wall": B.WALL_MAXWELL, "accommodation": -0.1}, B.EINVAL),
+    (_plate, {"wall": B.WALL_MAXWELL, "accommodation": 1.5}, B.EINVAL),
+    (_plate, {"wall": B.WALL_MAXWELL, "accommodation": float("nan")}, B.EINVAL),
+    (_plate, {"wall": 3}, B.EINVAL),
+    (_plate, {"abi_version": 1}, B.EABI),
 ])
 def test_required_bytes_validation(make, kw, code):
     with pytest.raises(P.LbmError) as e:
@@ -138,9 +144,11 @@ def test_required_bytes_sizes():
     P.required_bytes(p)
 
 
-def test_diffuse_wall_plate_is_accepted():
-    p = _plate(wall=B.WALL_DS)
-    assert P.required_bytes(p) == P.required_bytes(_plate())
+def test_diffuse_and_maxwell_walls_on_a_plate_are_accepted():
+    n = P.required_bytes(_plate())
+    assert P.required_bytes(_plate(wall=B.WALL_DS)) == n
+    for sigma in (0.0, 0.4, 1.0):
+        assert P.required_bytes(_plate(wall=B.WALL_MAXWELL, accommodation=sigma)) == n
 
 
 def test_beam_box_fits_one_gpu_with_room():
