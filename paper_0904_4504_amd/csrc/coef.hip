@@ -240,21 +240,43 @@ __device__ __forceinline__ void stage_load(const SolveDesc* __restrict__ descs, 
   const bool xper = d.geom != GEOM_BOX, yper = d.geom == GEOM_PERIODIC;
   const bool is_box = d.geom == GEOM_BOX;
   const int bx0 = d.bx0, bx1 = d.bx1, by0 = d.by0, by1 = d.by1;
+  // staged cell i = threadIdx.x + 256 it sits at (hx, hy) of the halo tile;
+  // step (hx, hy) instead of dividing per cell
+  constexpr int DX = 256 % HW, DY = 256 / HW;
+  int hx = (int)threadIdx.x % HW, hy = (int)threadIdx.x / HW;
+  // lattices narrower than the staged tile wrap more than once
+  const bool narrow = nx < HW || (yper && ny < T::HH);
 #pragma unroll
   for (int it = 0; it < T::NIT; ++it) {
     const int i = threadIdx.x + it * 256;
-    const int hx = i % HW, hy = i / HW;
     int gx = x0 - R + hx, gy = y0 - R + hy;
-    if (xper) gx = ((gx % nx) + nx) % nx;
-    if (yper) gy = ((gy % ny) + ny) % ny;
+    if (xper) {
+      gx += gx < 0 ? nx : 0;
+      gx -= gx >= nx ? nx : 0;
+    }
+    if (yper) {
+      gy += gy < 0 ? ny : 0;
+      gy -= gy >= ny ? ny : 0;
+    }
+    if (__builtin_expect(narrow, 0)) {
+      if (xper) gx = (((x0 - R + hx) % nx) + nx) % nx;
+      if (yper) gy = (((y0 - R + hy) % ny) + ny) % ny;
+    }
     const bool solid = is_box && gx >= bx0 && gx < bx1 && gy >= by0 && gy < by1;
     const bool load = i < NC && gx >= 0 && gx < nx && gy >= 0 && gy < ny && !solid;
-    // cells without data read a valid address and are zeroed below
-    const uint32_t o = load ? (uint32_t)(gy * ys + gx) * (uint32_t)sizeof(S) : 0u;
+    // cells without data read cell (0, 0) and are zeroed below
+    const int gxc = load ? gx : 0, gyc = load ? gy : 0;
+    const uint32_t o = (uint32_t)(gyc * ys + gxc) * (uint32_t)sizeof(S);
 #pragma unroll
     for (int k = 0; k < 6; ++k) c[it][k] = *at(pin[k], o);
 #pragma unroll
     for (int k = 0; k < 6; ++k) c[it][k] = load ? c[it][k] : S(0);
+    hx += DX;
+    hy += DY;
+    if (hx >= HW) {
+      hx -= HW;
+      ++hy;
+    }
   }
 }
 
