@@ -37,6 +37,40 @@
 
 namespace lbm {
 
+// Constants of a launch in the storage precision: the orbit weights, their
+// products with |vx| and vx^2 (the factors of the x-weighted sums; for
+// |vx| = 1 the weight itself is used) and the theta factors of the
+// coefficients.  Passed by value, so they sit in scalar registers.
+template <typename S>
+struct CoefConst {
+  S w[8];
+  S wx[8][4];   // w_o |vx|
+  S wxx[8][4];  // w_o vx^2
+  S theta;
+  S inv_theta;        // 1 / theta
+  S half_inv_theta;   // 1 / (2 theta)
+  S inv_theta2;       // 1 / theta^2
+  S half_inv_theta2;  // 1 / (2 theta^2)
+};
+
+template <typename S>
+CoefConst<S> coef_const(const KernelLattice& lat) {
+  CoefConst<S> c{};
+  for (int o = 0; o < 8; ++o) {
+    c.w[o] = (S)lat.w[o];
+    for (int a = 0; a < 4; ++a) {
+      c.wx[o][a] = (S)(lat.w[o] * a);
+      c.wxx[o][a] = (S)(lat.w[o] * a * a);
+    }
+  }
+  c.theta = (S)lat.theta;
+  c.inv_theta = (S)(1.0 / lat.theta);
+  c.half_inv_theta = (S)(0.5 / lat.theta);
+  c.inv_theta2 = (S)(1.0 / (lat.theta * lat.theta));
+  c.half_inv_theta2 = (S)(0.5 / (lat.theta * lat.theta));
+  return c;
+}
+
 namespace {
 
 // Index of velocity (vx, vy) in lattice L, or -1.
@@ -47,7 +81,13 @@ constexpr int find_q(int vx, int vy) {
   return -1;
 }
 
-constexpr int pmod(int a, int n) { return ((a % n) + n) % n; }
+template <typename S>
+__device__ __forceinline__ S fmadd(S a, S b, S c) {
+  if constexpr (sizeof(S) == 4)
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
 
 // Pointers into device global memory (loads and stores then address the
 // global segment directly, with a scalar base and a 32-bit lane offset).
@@ -109,7 +149,8 @@ constexpr bool source_used(int vx, int iy) {
 template <class L, typename S, bool DSW>
 __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<const S> min,
                                                       int x, int y, S ladd, double U,
-                                                      const KernelLattice& lat) {
+                                                      const KernelLattice& lat,
+                                                      const CoefConst<S>& cc) {
   const int64_t ks = d.mks;
   const int ys = (int)d.mys;
   const bool is_box = d.geom == GEOM_BOX;
@@ -161,7 +202,8 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<c
       }
     }
     if (py >= 0) {
-      const S wq = (S)lat.w[L::orbit[q]];
+      constexpr int o = L::orbit[q];
+      const S wq = cc.w[o];
       S f;
       if (DSW && diffuse) {
         double e = ds_arrival<vx>(d, U, cm, lat.w[L::orbit[q]], lat.theta);
@@ -188,7 +230,11 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<c
         if constexpr (vy != 0) p += S(-vy) * min[2 * ks + g] + S(vy * vy) * min[5 * ks + g];
         if constexpr (vx * vy != 0) p += S(vx * vy) * min[4 * ks + g];
         f = wq * p;
-        if (moving) f += (wq * S(vx)) * ladd;
+        if constexpr (vx != 0) {
+          constexpr int a = vx < 0 ? -vx : vx;
+          const S wa = a == 1 ? wq : cc.wx[o][a];
+          if (moving) f = fmadd(vx < 0 ? -wa : wa, ladd, f);
+        }
       }
       m.v[0] += f;
       if constexpr (vx != 0) m.v[1] += S(vx) * f;
@@ -213,103 +259,199 @@ struct CoefTile {
   static constexpr int NIT = (NC + 255) / 256;  // staged cells per thread
 };
 
-// Issue the loads of a tile's staged region (the tile and its R-cell halo)
-// into registers: body and outside cells as zeros, periodic images where the
-// geometry wraps.  No-op items stage nothing.
+namespace {
+
+// Two coefficients of a cell: (a0, bx), (by, cxx) or (cxy, cyy).
+template <typename S>
+using Pair = S __attribute__((ext_vector_type(2)));
+
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+
+// The same LDS address, opaque to the compiler: reads relative to it use
+// their small constant offsets directly instead of a new base register each.
+template <typename T>
+__device__ __forceinline__ lptr<const T> opaque(lptr<const T> p) {
+  uint32_t a = (uint32_t)(uintptr_t)p;
+  asm volatile("" : "+v"(a));
+  return (lptr<const T>)(uintptr_t)a;
+}
+
+// Raw buffer resource over `bytes` bytes at p (a wave-uniform address):
+// loads at offsets past the end return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, uint32_t bytes) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), 0, (int)bytes,
+                                           0x00020000);
+}
+
+template <typename S>
+__device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(S) == 4)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// An offset past the end of every plane (planes are below 2 GiB).
+constexpr uint32_t kNoCell = 0x80000000u;
+
+// Population that output row k pulls from the source cell at column offset
+// dx and row offset iy (both relative to the lane's column and the wave's
+// first output row), or -1.
+template <class L>
+constexpr int pull_q(int dx, int iy, int k) {
+  const int vy = k - iy;
+  if (vy < -L::R || vy > L::R) return -1;
+  return find_q<L>(-dx, vy);
+}
+
+// First column offset of source row iy that feeds output row k (with
+// vx != 0 if nz), or R + 1.
+template <class L>
+constexpr int first_dx(int iy, int k, bool nz) {
+  for (int dx = -L::R; dx <= L::R; ++dx)
+    if (pull_q<L>(dx, iy, k) >= 0 && (!nz || dx != 0)) return dx;
+  return L::R + 1;
+}
+
+}  // namespace
+
+// Read of memory that no thread writes during the launch, through the
+// constant address space: a scalar load (no wait on vector memory) for a
+// wave-uniform address.
+template <typename T>
+__device__ __forceinline__ T kread(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ WorkItem kread_item(const WorkItem* p) {
+  return WorkItem{kread(&p->solve), kread(&p->tile)};
+}
+
+// Step index and state buffers of a solve for this launch.
+template <typename S>
+struct TileCtx {
+  const S* min;  // input coefficients
+  S* mout;       // output coefficients
+  int64_t n;     // step index
+};
+
+template <typename S>
+__device__ __forceinline__ TileCtx<S> tile_ctx(const SolveDesc& d) {
+  const int64_t n = kread(&d.state->step);
+  void* const b0 = kread(&d.mbuf[0]);
+  void* const b1 = kread(&d.mbuf[1]);
+  return {static_cast<const S*>(n & 1 ? b1 : b0), static_cast<S*>(n & 1 ? b0 : b1), n};
+}
+
+// Load a tile's staged region (the tile and its R-cell halo) into registers:
+// body and outside cells as zeros, periodic images where the geometry wraps.
 template <class L, typename S, int RB>
-__device__ __forceinline__ void stage_load(const SolveDesc* __restrict__ descs, WorkItem wi,
-                                           S (&c)[CoefTile<L, RB>::NIT][6]) {
+__device__ __forceinline__ void stage_load(const SolveDesc& d, const TileCtx<S>& t, int tile,
+                                           S (&c)[CoefTile<L, RB>::NIT][6], int tid) {
   using T = CoefTile<L, RB>;
   constexpr int R = T::R, HW = T::HW, NC = T::NC;
-#pragma unroll
-  for (int it = 0; it < T::NIT; ++it)
-#pragma unroll
-    for (int k = 0; k < 6; ++k) c[it][k] = S(0);
-  if (wi.tile < 0) return;
-  const SolveDesc& d = descs[wi.solve];
-  const int64_t n = d.state->step;
-  const gptr<const S> min = as_global(static_cast<const S*>(d.mbuf[n & 1]));
+  const S* min = t.min;
   const int nx = d.nx, ny = d.ny;
   const int64_t ks = d.mks;
   const int ys = (int)d.mys;
-  gptr<const S> pin[6];
+  const uint32_t bytes = (uint32_t)ny * (uint32_t)ys * (uint32_t)sizeof(S);
+  __amdgpu_buffer_rsrc_t rs[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) pin[k] = scalar_ptr(min + k * ks);
-  const int x0 = (wi.tile % d.tiles_x) * kCoefTileW;
-  const int y0 = (wi.tile / d.tiles_x) * T::TH;
+  for (int k = 0; k < 6; ++k) rs[k] = plane_rsrc(min + k * ks, bytes);
+  const int x0 = (tile % d.tiles_x) * kCoefTileW;
+  const int y0 = (tile / d.tiles_x) * T::TH;
   const bool xper = d.geom != GEOM_BOX, yper = d.geom == GEOM_PERIODIC;
   const bool is_box = d.geom == GEOM_BOX;
   const int bx0 = d.bx0, bx1 = d.bx1, by0 = d.by0, by1 = d.by1;
-  // staged cell i = threadIdx.x + 256 it sits at (hx, hy) of the halo tile;
-  // step (hx, hy) instead of dividing per cell
+  // staged cell i = tid + 256 it sits at (hx, hy) of the halo tile; step
+  // (hx, hy) instead of dividing per cell
   constexpr int DX = 256 % HW, DY = 256 / HW;
-  int hx = (int)threadIdx.x % HW, hy = (int)threadIdx.x / HW;
-  // lattices narrower than the staged tile wrap more than once
-  const bool narrow = nx < HW || (yper && ny < T::HH);
+  int hx = tid % HW, hy = tid / HW;
+  // byte offsets of the staged cells first, then the loads (one code path,
+  // so the wait before each use covers exactly the loads it needs)
+  uint32_t o[T::NIT];
+  // a staged region inside the lattice, clear of the body: every cell is
+  // read as is (cells past the region read past it, within or beyond the
+  // plane, and are not stored)
+  const bool inside = x0 >= R && x0 + kCoefTileW + R <= nx && y0 >= R && y0 + T::TH + R <= ny &&
+                      !(is_box && x0 - R < bx1 && x0 + kCoefTileW + R > bx0 && y0 - R < by1 &&
+                        y0 + T::TH + R > by0);
+  if (inside) {
+    constexpr uint32_t es = sizeof(S);
+    uint32_t oi = (uint32_t)((y0 - R + hy) * ys + x0 - R + hx) * es;
+    const uint32_t step = (uint32_t)(DY * ys + DX) * es, wrap = (uint32_t)(ys - HW) * es;
 #pragma unroll
-  for (int it = 0; it < T::NIT; ++it) {
-    const int i = threadIdx.x + it * 256;
-    int gx = x0 - R + hx, gy = y0 - R + hy;
-    if (xper) {
-      gx += gx < 0 ? nx : 0;
-      gx -= gx >= nx ? nx : 0;
+    for (int it = 0; it < T::NIT; ++it) {
+      o[it] = oi;
+      oi += step;
+      hx += DX;
+      if (hx >= HW) {
+        hx -= HW;
+        oi += wrap;
+      }
     }
-    if (yper) {
-      gy += gy < 0 ? ny : 0;
-      gy -= gy >= ny ? ny : 0;
-    }
-    if (__builtin_expect(narrow, 0)) {
-      if (xper) gx = (((x0 - R + hx) % nx) + nx) % nx;
-      if (yper) gy = (((y0 - R + hy) % ny) + ny) % ny;
-    }
-    const bool solid = is_box && gx >= bx0 && gx < bx1 && gy >= by0 && gy < by1;
-    const bool load = i < NC && gx >= 0 && gx < nx && gy >= 0 && gy < ny && !solid;
-    // cells without data read cell (0, 0) and are zeroed below
-    const int gxc = load ? gx : 0, gyc = load ? gy : 0;
-    const uint32_t o = (uint32_t)(gyc * ys + gxc) * (uint32_t)sizeof(S);
+  } else {
+    // lattices narrower than the staged tile wrap more than once
+    const bool narrow = nx < HW || (yper && ny < T::HH);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) c[it][k] = *at(pin[k], o);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) c[it][k] = load ? c[it][k] : S(0);
-    hx += DX;
-    hy += DY;
-    if (hx >= HW) {
-      hx -= HW;
-      ++hy;
+    for (int it = 0; it < T::NIT; ++it) {
+      const int i = tid + it * 256;
+      int gx = x0 - R + hx, gy = y0 - R + hy;
+      if (xper) {
+        gx += gx < 0 ? nx : 0;
+        gx -= gx >= nx ? nx : 0;
+      }
+      if (yper) {
+        gy += gy < 0 ? ny : 0;
+        gy -= gy >= ny ? ny : 0;
+      }
+      if (__builtin_expect(narrow, 0)) {
+        if (xper) gx = (((x0 - R + hx) % nx) + nx) % nx;
+        if (yper) gy = (((y0 - R + hy) % ny) + ny) % ny;
+      }
+      const bool solid = is_box && gx >= bx0 && gx < bx1 && gy >= by0 && gy < by1;
+      const bool load = i < NC && gx >= 0 && gx < nx && gy >= 0 && gy < ny && !solid;
+      // cells without data read past the end of the plane: zeros
+      o[it] = load ? (uint32_t)(gy * ys + gx) * (uint32_t)sizeof(S) : kNoCell;
+      hx += DX;
+      hy += DY;
+      if (hx >= HW) {
+        hx -= HW;
+        ++hy;
+      }
     }
   }
+#pragma unroll
+  for (int it = 0; it < T::NIT; ++it)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c[it][k] = buf_load<S>(rs[k], o[it]);
 }
 
-// Moments, bounce-back corrections, collision and store of the RB cells of
-// this thread, from the staged tile in LDS.
+// Moments, bounce-back corrections and collision of the RB cells of this
+// thread, from the staged tile in LDS (staged row r holds the pairs
+// (a0, bx), (by, cxx), (cxy, cyy) of its HW cells as three runs of HW): the
+// new coefficients of the cells in the lattice and the fluid go to res.
 template <class L, typename S, int RB, bool DSW>
-__device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
-                                             const S (&C)[6][CoefTile<L, RB>::NC],
-                                             const KernelLattice& lat) {
+__device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S>& t, int tile,
+                                             const Pair<S>* C, const KernelLattice& lat,
+                                             const CoefConst<S>& cc, int tid,
+                                             S (&res)[RB][6]) {
   using T = CoefTile<L, RB>;
   constexpr int R = T::R, HW = T::HW;
-  const int64_t n = d.state->step;
-  const gptr<const S> min = as_global(static_cast<const S*>(d.mbuf[n & 1]));
-  const gptr<S> mout = as_global(static_cast<S*>(d.mbuf[(n & 1) ^ 1]));
+  const int64_t n = t.n;
+  const gptr<const S> min = as_global(t.min);
   const int nx = d.nx, ny = d.ny;
-  const int64_t ks = d.mks;
-  const int ys = (int)d.mys;
-  gptr<S> pout[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) pout[k] = scalar_ptr(mout + k * ks);
   const int x0 = (tile % d.tiles_x) * kCoefTileW;
   const int y0 = (tile / d.tiles_x) * T::TH;
   const bool is_box = d.geom == GEOM_BOX;
   const int bx0 = d.bx0, bx1 = d.bx1, by0 = d.by0, by1 = d.by1;
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
   const int x = x0 + lane, yb = y0 + wave * RB;
-  S wo[L::NORB];
-#pragma unroll
-  for (int k = 0; k < L::NORB; ++k) wo[k] = (S)lat.w[k];
-  // staged cell of the lane's column + dx in the wave's source row iy
-  // (iy = -R .. RB - 1 + R relative to the wave's first output row)
-  const int cbase = (wave * RB + R) * HW + lane + R;
 
   Mom<S> acc[RB];
 #pragma unroll
@@ -319,6 +461,9 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
 
   static_for<0, RB + 2 * R>([&](auto ic) __attribute__((always_inline)) {
     constexpr int iy = decltype(ic)::value - R;
+    // staged row of source row iy, from the cell at column offset -R
+    const lptr<const Pair<S>> row =
+        opaque((lptr<const Pair<S>>)(C + (wave * RB + R + iy) * 3 * HW + lane));
     // per output row k (pulling along vy = k - iy): sums of w f, w vx f, w vx^2 f
     S t0[RB], t1[RB], t2[RB];
 #pragma unroll
@@ -327,27 +472,39 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
       constexpr int dx = decltype(dxc)::value - R;
       constexpr int vx = -dx;  // the source x - v sits at x + dx
       if constexpr (source_used<L, RB>(vx, iy)) {
-        const int ci = cbase + iy * HW + dx;
-        // coefficients a0, bx, by, cxx, cxy, cyy of the source cell
-        S g = C[0][ci];
-        if constexpr (vx != 0) g += S(vx) * C[1][ci] + S(vx * vx) * C[3][ci];
-        S h = C[2][ci];
-        if constexpr (vx != 0) h += S(vx) * C[4][ci];
-        const S cyy = C[5][ci];
+        const Pair<S> p0 = row[dx + R], p1 = row[HW + dx + R], p2 = row[2 * HW + dx + R];
+        // populations of the source cell along vx: f = g + vy^2 cyy + vy h
+        S g = p0.x, h = p1.x;
+        if constexpr (vx != 0) {
+          g = fmadd(S(vx * vx), p1.y, fmadd(S(vx), p0.y, g));
+          h = fmadd(S(vx), p2.x, h);
+        }
+        const S cyy = p2.y;
         static_for<0, RB>([&](auto kc) __attribute__((always_inline)) {
           constexpr int k = decltype(kc)::value;
           constexpr int vy = k - iy;
-          if constexpr (vy >= -R && vy <= R && find_q<L>(vx, vy) >= 0) {
-            constexpr int q = find_q<L>(vx, vy);
+          constexpr int q = pull_q<L>(dx, iy, k);
+          if constexpr (q >= 0) {
+            constexpr int o = L::orbit[q];
             S f = g;
-            if constexpr (vy != 0) f = (g + S(vy * vy) * cyy) + S(vy) * h;
-            // integer factors vx, vx^2 become instruction constants; only
-            // the NORB weights occupy registers
-            const S u = wo[L::orbit[q]] * f;
-            t0[k] += u;
+            if constexpr (vy != 0) f = fmadd(S(vy), h, fmadd(S(vy * vy), cyy, g));
+            const S w = cc.w[o];
+            if constexpr (dx == first_dx<L>(iy, k, false))
+              t0[k] = w * f;
+            else
+              t0[k] = fmadd(w, f, t0[k]);
             if constexpr (vx != 0) {
-              t1[k] += S(vx) * u;
-              t2[k] += S(vx * vx) * u;
+              constexpr int a = vx < 0 ? -vx : vx;
+              const S wa = a == 1 ? w : cc.wx[o][a];
+              const S wb = a == 1 ? w : cc.wxx[o][a];
+              const S wsx = vx < 0 ? -wa : wa;
+              if constexpr (dx == first_dx<L>(iy, k, true)) {
+                t1[k] = wsx * f;
+                t2[k] = wb * f;
+              } else {
+                t1[k] = fmadd(wsx, f, t1[k]);
+                t2[k] = fmadd(wb, f, t2[k]);
+              }
             }
           }
         });
@@ -358,13 +515,23 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
       constexpr int vy = k - iy;
       if constexpr (vy >= -R && vy <= R) {
         Mom<S>& m = acc[k];
-        m.v[0] += t0[k];
-        m.v[1] += t1[k];
-        m.v[3] += t2[k];
-        if constexpr (vy != 0) {
-          m.v[2] += S(vy) * t0[k];
-          m.v[4] += S(vy) * t1[k];
-          m.v[5] += S(vy * vy) * t0[k];
+        if constexpr (iy == k - R) {
+          // first source row of output row k
+          m.v[0] = t0[k];
+          m.v[1] = t1[k];
+          m.v[3] = t2[k];
+          m.v[2] = S(vy) * t0[k];
+          m.v[4] = S(vy) * t1[k];
+          m.v[5] = S(vy * vy) * t0[k];
+        } else {
+          m.v[0] += t0[k];
+          m.v[1] += t1[k];
+          m.v[3] += t2[k];
+          if constexpr (vy != 0) {
+            m.v[2] = fmadd(S(vy), t0[k], m.v[2]);
+            m.v[4] = fmadd(S(vy), t1[k], m.v[4]);
+            m.v[5] = fmadd(S(vy * vy), t0[k], m.v[5]);
+          }
         }
       }
     });
@@ -385,23 +552,28 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
   const bool far_band = d.geom == GEOM_PLATE && d.far == FAR_WALL;
   const bool wave_has_wall = (x0 < wx1 && x0 + kCoefTileW > wx0 && yb < wy1 && yb + RB > wy0) ||
                              (far_band && yb + RB > ny - R);
-  S ladd = S(0);
-  if (wave_has_wall) ladd = (S)(d.ladd_scale * d.drive[n].u);
 
-  const S th = (S)lat.theta;
-  const S inv_th = (S)(1.0 / lat.theta);
-  const S h2 = (S)(0.5 / (lat.theta * lat.theta));
+  const S th = cc.theta;
+  const S inv_th = cc.inv_theta;
+  const S h2 = cc.half_inv_theta2;
   const S om = (S)d.inv_tau;
   const S rho0 = (S)d.rho0;
-#pragma unroll
-  for (int k = 0; k < RB; ++k) {
+  // (a compile-time loop: unrolled whatever the size of the wall code)
+  static_for<0, RB>([&](auto kc) __attribute__((always_inline)) {
+    constexpr int k = decltype(kc)::value;
     Mom<S> m = acc[k];
     const int y = yb + k;
-    if (y >= ny || x >= nx) continue;
-    if (is_box && y >= by0 && y < by1 && x >= bx0 && x < bx1) continue;  // solid
+    if (y >= ny || x >= nx) return;
+    if (is_box && y >= by0 && y < by1 && x >= bx0 && x < bx1) return;  // solid
     if (wave_has_wall) {
       const bool near = (y >= wy0 && y < wy1 && x >= wx0 && x < wx1) || (far_band && y >= ny - R);
-      if (near) m = add_links<L, S, DSW>(m, d, min, x, y, ladd, d.drive[n].u, lat);
+      if (near) {
+        const double U = kread(&d.drive[n].u);
+        S ladd = (S)(d.ladd_scale * U);
+        // computed per cell in the band: keeps its products out of the common path
+        asm volatile("" : "+v"(ladd));
+        m = add_links<L, S, DSW>(m, d, min, x, y, ladd, U, lat, cc);
+      }
     }
     const S drho = m.v[0], jx = m.v[1], jy = m.v[2];
     const S rho = rho0 + drho;
@@ -416,53 +588,105 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, int tile,
     const S bxx = axx - om * (axx - uxx);
     const S bxy = axy - om * (axy - uxy);
     const S byy = ayy - om * (ayy - uyy);
+    res[k][0] = drho - (bxx + byy) * cc.half_inv_theta;
+    res[k][1] = jx * inv_th;
+    res[k][2] = jy * inv_th;
+    res[k][3] = bxx * h2;
+    res[k][4] = bxy * cc.inv_theta2;
+    res[k][5] = byy * h2;
+  });
+}
+
+// Store the new coefficients of this thread's cells (those in the lattice
+// and the fluid).
+template <class L, typename S, int RB>
+__device__ __forceinline__ void store_tile(const SolveDesc& d, const TileCtx<S>& t, int tile,
+                                           int tid, const S (&res)[RB][6]) {
+  using T = CoefTile<L, RB>;
+  const gptr<S> mout = as_global(t.mout);
+  const int nx = d.nx, ny = d.ny;
+  const int64_t ks = d.mks;
+  const int ys = (int)d.mys;
+  gptr<S> pout[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) pout[k] = scalar_ptr(mout + k * ks);
+  const bool is_box = d.geom == GEOM_BOX;
+  const int x = (tile % d.tiles_x) * kCoefTileW + (tid & 63);
+  const int yb = (tile / d.tiles_x) * T::TH + (tid >> 6) * RB;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int y = yb + k;
+    if (y >= ny || x >= nx) continue;
+    if (is_box && y >= d.by0 && y < d.by1 && x >= d.bx0 && x < d.bx1) continue;  // solid
     const uint32_t o = (uint32_t)(y * ys + x) * (uint32_t)sizeof(S);
     // the output is not re-read in this step: stream it past the caches
-    __builtin_nontemporal_store(drho - (bxx + byy) * (S(0.5) * inv_th), at(pout[0], o));
-    __builtin_nontemporal_store(jx * inv_th, at(pout[1], o));
-    __builtin_nontemporal_store(jy * inv_th, at(pout[2], o));
-    __builtin_nontemporal_store(bxx * h2, at(pout[3], o));
-    __builtin_nontemporal_store(bxy * (S(2) * h2), at(pout[4], o));
-    __builtin_nontemporal_store(byy * h2, at(pout[5], o));
+#pragma unroll
+    for (int j = 0; j < 6; ++j) __builtin_nontemporal_store(res[k][j], at(pout[j], o));
+  }
+}
+
+// Write a loaded tile (stage_load) to LDS.
+template <class L, typename S, int RB>
+__device__ __forceinline__ void stage_store(Pair<S>* C, const S (&c)[CoefTile<L, RB>::NIT][6],
+                                            int tid) {
+  using T = CoefTile<L, RB>;
+  // staged cell tid + 256 it of the halo tile, at (hx, hy)
+  constexpr int DX = 256 % T::HW, DY = 256 / T::HW;
+  int hx = tid % T::HW, hy = tid / T::HW;
+#pragma unroll
+  for (int it = 0; it < T::NIT; ++it) {
+    if (tid + it * 256 < T::NC)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        C[(hy * 3 + j) * T::HW + hx] = Pair<S>{c[it][2 * j], c[it][2 * j + 1]};
+    hx += DX;
+    hy += DY;
+    if (hx >= T::HW) {
+      hx -= T::HW;
+      ++hy;
+    }
   }
 }
 
 // DSW: with the diffuse-scattering wall (a separate instantiation, so that
-// the bounce-back kernel carries none of its code).
+// the bounce-back kernel carries none of its code).  One workgroup per work
+// item.
 template <class L, typename S, int RB, bool DSW>
 __global__ __launch_bounds__(256) void coef_kernel(const SolveDesc* __restrict__ descs,
                                                    const WorkItem* __restrict__ work,
-                                                   KernelLattice lat) {
+                                                   KernelLattice lat, CoefConst<S> cc) {
   using T = CoefTile<L, RB>;
-  // one array per coefficient, so that every LDS read of a coefficient is a
-  // 32-bit (64-bit) load at consecutive lanes
-  __shared__ S C[6][T::NC];
-  const WorkItem wi = work[blockIdx.x];
+  // staged row r, pair j, column c at C[(3 r + j) HW + c]: the reads of a
+  // pair are 64-bit (128-bit) loads at consecutive lanes
+  __shared__ Pair<S> C[T::HH * 3 * T::HW];
+  const WorkItem wi = kread_item(&work[blockIdx.x]);
   if (wi.tile < 0) return;
-  // all loads of a thread are issued before the first LDS store, so the
-  // block waits for one memory round trip, not one per staged cell
-  S c[T::NIT][6];
-  stage_load<L, S, RB>(descs, wi, c);
-#pragma unroll
-  for (int it = 0; it < T::NIT; ++it) {
-    const int i = threadIdx.x + it * 256;
-    if (i < T::NC)
-#pragma unroll
-      for (int k = 0; k < 6; ++k) C[k][i] = c[it][k];
+  const SolveDesc& d = descs[wi.solve];
+  const TileCtx<S> ctx = tile_ctx<S>(d);
+  const int tid = (int)threadIdx.x;
+  {
+    // all loads of a thread are issued before the first LDS store, so the
+    // block waits for one memory round trip, not one per staged cell
+    S c[T::NIT][6];
+    stage_load<L, S, RB>(d, ctx, wi.tile, c, tid);
+    stage_store<L, S, RB>(C, c, tid);
   }
   __syncthreads();
-  compute_tile<L, S, RB, DSW>(descs[wi.solve], wi.tile, C, lat);
+  S res[RB][6];
+  compute_tile<L, S, RB, DSW>(d, ctx, wi.tile, C, lat, cc, tid, res);
+  store_tile<L, S, RB>(d, ctx, wi.tile, tid, res);
 }
 
 template <class L, typename S, int RB>
 static hipError_t launch_rb(bool ds, const SolveDesc* descs, const WorkItem* work, int nwork,
                             const KernelLattice& lat, hipStream_t stream) {
+  const CoefConst<S> cc = coef_const<S>(lat);
   if (ds)
     hipLaunchKernelGGL((coef_kernel<L, S, RB, true>), dim3(nwork), dim3(256), 0, stream, descs,
-                       work, lat);
+                       work, lat, cc);
   else
     hipLaunchKernelGGL((coef_kernel<L, S, RB, false>), dim3(nwork), dim3(256), 0, stream, descs,
-                       work, lat);
+                       work, lat, cc);
   return hipGetLastError();
 }
 
