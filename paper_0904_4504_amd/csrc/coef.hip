@@ -254,9 +254,10 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<c
 template <class L, int RB>
 struct CoefTile {
   static constexpr int R = L::R;
-  static constexpr int TH = 4 * RB;  // tile rows
+  static constexpr int NT = 64 * kCoefWaves;  // threads
+  static constexpr int TH = kCoefWaves * RB;  // tile rows
   static constexpr int HW = kCoefTileW + 2 * R, HH = TH + 2 * R, NC = HW * HH;
-  static constexpr int NIT = (NC + 255) / 256;  // staged cells per thread
+  static constexpr int NIT = (NC + NT - 1) / NT;  // staged cells per thread
 };
 
 namespace {
@@ -367,9 +368,9 @@ __device__ __forceinline__ void stage_load(const SolveDesc& d, const TileCtx<S>&
   const bool xper = d.geom != GEOM_BOX, yper = d.geom == GEOM_PERIODIC;
   const bool is_box = d.geom == GEOM_BOX;
   const int bx0 = d.bx0, bx1 = d.bx1, by0 = d.by0, by1 = d.by1;
-  // staged cell i = tid + 256 it sits at (hx, hy) of the halo tile; step
+  // staged cell i = tid + NT it sits at (hx, hy) of the halo tile; step
   // (hx, hy) instead of dividing per cell
-  constexpr int DX = 256 % HW, DY = 256 / HW;
+  constexpr int DX = T::NT % HW, DY = T::NT / HW;
   int hx = tid % HW, hy = tid / HW;
   // byte offsets of the staged cells first, then the loads (one code path,
   // so the wait before each use covers exactly the loads it needs)
@@ -399,7 +400,7 @@ __device__ __forceinline__ void stage_load(const SolveDesc& d, const TileCtx<S>&
     const bool narrow = nx < HW || (yper && ny < T::HH);
 #pragma unroll
     for (int it = 0; it < T::NIT; ++it) {
-      const int i = tid + it * 256;
+      const int i = tid + it * T::NT;
       int gx = x0 - R + hx, gy = y0 - R + hy;
       if (xper) {
         gx += gx < 0 ? nx : 0;
@@ -630,12 +631,12 @@ template <class L, typename S, int RB>
 __device__ __forceinline__ void stage_store(Pair<S>* C, const S (&c)[CoefTile<L, RB>::NIT][6],
                                             int tid) {
   using T = CoefTile<L, RB>;
-  // staged cell tid + 256 it of the halo tile, at (hx, hy)
-  constexpr int DX = 256 % T::HW, DY = 256 / T::HW;
+  // staged cell tid + NT it of the halo tile, at (hx, hy)
+  constexpr int DX = T::NT % T::HW, DY = T::NT / T::HW;
   int hx = tid % T::HW, hy = tid / T::HW;
 #pragma unroll
   for (int it = 0; it < T::NIT; ++it) {
-    if (tid + it * 256 < T::NC)
+    if (tid + it * T::NT < T::NC)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         C[(hy * 3 + j) * T::HW + hx] = Pair<S>{c[it][2 * j], c[it][2 * j + 1]};
@@ -652,7 +653,7 @@ __device__ __forceinline__ void stage_store(Pair<S>* C, const S (&c)[CoefTile<L,
 // the bounce-back kernel carries none of its code).  One workgroup per work
 // item.
 template <class L, typename S, int RB, bool DSW>
-__global__ __launch_bounds__(256) void coef_kernel(const SolveDesc* __restrict__ descs,
+__global__ __launch_bounds__(64 * kCoefWaves) void coef_kernel(const SolveDesc* __restrict__ descs,
                                                    const WorkItem* __restrict__ work,
                                                    KernelLattice lat, CoefConst<S> cc) {
   using T = CoefTile<L, RB>;
@@ -682,10 +683,10 @@ static hipError_t launch_rb(bool ds, const SolveDesc* descs, const WorkItem* wor
                             const KernelLattice& lat, hipStream_t stream) {
   const CoefConst<S> cc = coef_const<S>(lat);
   if (ds)
-    hipLaunchKernelGGL((coef_kernel<L, S, RB, true>), dim3(nwork), dim3(256), 0, stream, descs,
+    hipLaunchKernelGGL((coef_kernel<L, S, RB, true>), dim3(nwork), dim3(64 * kCoefWaves), 0, stream, descs,
                        work, lat, cc);
   else
-    hipLaunchKernelGGL((coef_kernel<L, S, RB, false>), dim3(nwork), dim3(256), 0, stream, descs,
+    hipLaunchKernelGGL((coef_kernel<L, S, RB, false>), dim3(nwork), dim3(64 * kCoefWaves), 0, stream, descs,
                        work, lat, cc);
   return hipGetLastError();
 }

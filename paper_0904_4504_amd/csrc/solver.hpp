@@ -13,7 +13,8 @@ constexpr int kCoefKDefault = 2;
 
 // Rows of a coefficient-kernel tile of variant K: four wavefronts of K rows
 // each (K cells per thread).
-__host__ __device__ constexpr int coef_tile_rows(int K) { return 4 * K; }
+constexpr int kCoefWaves = 4;    // coefficient kernel: wavefronts per workgroup
+__host__ __device__ constexpr int coef_tile_rows(int K) { return kCoefWaves * K; }
 constexpr int kMaxSlots = 1 << 20;
 
 enum Geom : int32_t { GEOM_PLATE = 0, GEOM_BOX = 1, GEOM_PERIODIC = 2 };
