@@ -80,6 +80,29 @@ def workload(name, steps, warmup):
     return solves, desc
 
 
+def copy_ceiling(stream, nbytes=1 << 31, reps=5):
+    """Rate of torch's device-to-device copy of nbytes on this GPU (bytes read
+    plus written per second, GB/s): a measured copy ceiling next to the 8 TB/s
+    datasheet peak (a float4 copy kernel of our own reaches about 6.2 TB/s,
+    so this one is a floor on what a copy can do)."""
+    import torch
+    with torch.cuda.stream(stream):
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
 def traffic_from_profile(repr_):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
     taken on the current kernel source; else None."""
@@ -293,7 +316,9 @@ def main():
     launch_bytes = bytes_per_lu * cells
     hbm_gbs = launch_bytes / avg_kernel_s / 1e9
     traffic = traffic_from_profile(repr_)
+    copy_gbs = copy_ceiling(stream)
     hbm = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
+           "torch_copy": copy_gbs, "frac_of_torch_copy": hbm_gbs / copy_gbs,
            "algorithmic_bytes_per_launch": launch_bytes, "traffic": traffic}
     kernel = KERNELS[repr_][0].format(rb=a.tile or 2)  # tile 0: 2 cells per thread
     if repr_ == 1:

@@ -389,6 +389,47 @@ def _alone(P, s, stream):
         return fx, fy, sv.get_populations()
 
 
+def test_batch_sweep_subsample_matches_oracle(P):
+    """The 256-solve sweep draw, on a seeded subsample: its smallest and its
+    largest solve and two drawn at random, each from a perturbed rest state,
+    truncated to 24 steps and advanced as one batch (FP32 deviation storage,
+    the representation the library picks); every step's force against the
+    FP64 oracle within the short-run FP32 bound."""
+    import torch
+    draw = W.batch_sweep()
+    cells = [s.nx * s.ny for s in draw]
+    rng = np.random.default_rng(4)
+    pick = {int(np.argmin(cells)), int(np.argmax(cells))}
+    while len(pick) < 4:
+        pick.add(int(rng.integers(0, len(draw))))
+    solves = [draw[i].scaled(24, 16) for i in sorted(pick)]
+    v, w, th = P.lattice(37)
+    stream = torch.cuda.Stream()
+    f0s, svs = [], []
+    for k, s in enumerate(solves):
+        print(f"case {s.name} {s.nx}x{s.ny} box {s.box} tau {s.tau:.4g}", flush=True)
+        f0s.append(_f0(s, w, seed=100 + k, amp=1e-3))
+        sv = P.Solver(P.params_from_solve(s), stream=stream)
+        sv.set_populations(f0s[-1])
+        svs.append(sv)
+    b = P.Batch(stream)
+    try:
+        for sv in svs:
+            b.add(sv)
+        b.step(24)
+        b.synchronize()
+        for s, sv, f0 in zip(solves, svs, f0s):
+            fx, fy = sv.force_history(0, s.nsteps)
+            ox, oy, _ = O.run(_oracle_params(s), s.nsteps, f0=f0)
+            fscale = max(np.max(np.abs(ox)), np.max(np.abs(oy)))
+            assert np.max(np.abs(fx - ox)) <= 2e-5 * fscale, s.name
+            assert np.max(np.abs(fy - oy)) <= 2e-5 * fscale, s.name
+    finally:
+        b.close()
+        for sv in svs:
+            sv.close()
+
+
 @pytest.mark.parametrize("graphs", [0, 8])
 def test_batch_alone_equals_mix(P, graphs):
     """Uneven lattices in one fused launch, one member joining late and one
