@@ -322,14 +322,17 @@ def main():
            "algorithmic_bytes_per_launch": launch_bytes, "traffic": traffic}
     kernel = KERNELS[repr_][0].format(rb=a.tile or 2)  # tile 0: 2 cells per thread
     if repr_ == 1:
-        # populations: 296 B per update at ~1 kflop -> bound by HBM
+        # populations: 296 B per update at ~1 kflop (3.4 flop/B) -> bound by HBM
         roofline = dict(hbm, bound="hbm")
     else:
-        # coefficients: 48 B and ~0.4 kflop per update -> bound by the vector ALUs
+        # coefficients: 48 B and 418 flop per update (8.7 flop/B), just below
+        # the ridge of the FP32 vector units over HBM (78.6 / 8.0 = 9.8 flop/B),
+        # so the roofline bound is HBM; the vector-ALU figures go alongside
         tflops = COEF_FLOPS_PER_LU * cells / avg_kernel_s / 1e12
-        roofline = {"bound": "alu", "achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": tflops / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
-                    "flops_per_update": COEF_FLOPS_PER_LU}
+        roofline = dict(hbm, bound="hbm")
+        roofline["alu"] = {"achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": tflops / FP32_VALU_PEAK_TFLOPS,
+                           "flops_per_update": COEF_FLOPS_PER_LU}
     roofline.update({"kernel": kernel, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches,
                      "kernel_timing": "HIP events around each launch, a second pass of the same "
                                       "number of steps after the timed one"})
