@@ -255,19 +255,11 @@ template <typename S>
 __device__ void finalize_solve(const SolveDesc& d, int mode) {
   SolveState* st = d.state;
   const int64_t n = st->step;
-  // the loads that depend only on n are issued together, early: the
-  // kernel is a chain of memory round trips
-  const Drive dr = d.drive[n];
-  double lk[6];
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < 6; ++k) lk[k] = st->lockin[k];
   const bool coeffs = mode == 1 || (mode == 2 && d.mbuf[0] != nullptr);
   double fx = 0.0, fy = 0.0, fm = 0.0;
   if (coeffs) {
-    const S* __restrict__ c = static_cast<const S*>(n & 1 ? d.mbuf[1] : d.mbuf[0]);
+    const S* __restrict__ c = static_cast<const S*>(d.mbuf[n & 1]);
     const int64_t ks = d.mks;
-#pragma unroll 2
     for (int i = threadIdx.x; i < d.nfcells; i += kBlock) {
       const ForceCell& fc = d.fcells[i];
 #pragma unroll
@@ -301,6 +293,7 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    const Drive dr = d.drive[n];
     double sx = 0.0, sy = 0.0, sm = 0.0;
 #pragma unroll
     for (int k = 0; k < kBlock / 64; ++k) {
@@ -326,12 +319,12 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
     d.hist[2 * h] = fx;
     d.hist[2 * h + 1] = fy;
     if (n >= d.lockin_first && n < d.lockin_first + d.lockin_count) {
-      st->lockin[0] = lk[0] + fx * dr.s;
-      st->lockin[1] = lk[1] + fx * dr.c;
-      st->lockin[2] = lk[2] + fx;
-      st->lockin[3] = lk[3] + fy * dr.s;
-      st->lockin[4] = lk[4] + fy * dr.c;
-      st->lockin[5] = lk[5] + fy;
+      st->lockin[0] += fx * dr.s;
+      st->lockin[1] += fx * dr.c;
+      st->lockin[2] += fx;
+      st->lockin[3] += fy * dr.s;
+      st->lockin[4] += fy * dr.c;
+      st->lockin[5] += fy;
     }
     st->step = n + 1;
   }
