@@ -622,9 +622,11 @@ __device__ __forceinline__ void store_tile(const SolveDesc& d, const TileCtx<S>&
     if (y >= ny || x >= nx) continue;
     if (is_box && y >= d.by0 && y < d.by1 && x >= d.bx0 && x < d.bx1) continue;  // solid
     const uint32_t o = (uint32_t)(y * ys + x) * (uint32_t)sizeof(S);
-    // the output is not re-read in this step: stream it past the caches
+    // plain (cached) stores: the next step reads these planes back, and a
+    // state of 48 B per cell stays in the last-level cache between steps
+    // (nontemporal stores: 52.3 against 50.9 us per launch on the beam box)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) __builtin_nontemporal_store(res[k][j], at(pout[j], o));
+    for (int j = 0; j < 6; ++j) *at(pout[j], o) = res[k][j];
   }
 }
 
