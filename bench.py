@@ -294,8 +294,9 @@ def main():
         torch.cuda.synchronize()
         batch.synchronize()
         elapsed_ms = t0.elapsed_time(t1)
-        # then as many steps again with HIP events around every launch of the
-        # step kernel (eager launches): its average duration for the roofline
+        # then as many steps again, eagerly, each launch of the step kernel
+        # recording its own start and stop events: its average duration for
+        # the roofline
         batch.timing(True)
         batch.step(a.steps)
         batch.synchronize()
@@ -334,8 +335,9 @@ def main():
                            "frac": tflops / FP32_VALU_PEAK_TFLOPS,
                            "flops_per_update": COEF_FLOPS_PER_LU}
     roofline.update({"kernel": kernel, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches,
-                     "kernel_timing": "HIP events around each launch, a second pass of the same "
-                                      "number of steps after the timed one"})
+                     "kernel_timing": "start and stop events recorded by each launch itself "
+                                      "(extended launch), a second pass of the same number of "
+                                      "steps after the timed one"})
     out = {
         "metric": METRIC,
         "value": mlups,

@@ -136,14 +136,16 @@ int collect_timing(lbm_batch* b) {
 int launch_one(lbm_batch* b) {
   const bool f64 = b->storage == LBM_STORE_F64, bgk = b->collision == LBM_COLL_BGK;
   const KernelLattice& lat = b->active[0]->klat;
-  auto step = [&]() {
+  // ev: the launch records its own start and end (the timed kernel is the
+  // only step kernel of the launch set)
+  auto step = [&](KernelEvents ev) {
     hipError_t e = hipSuccess;
     if (b->nwork > 0)
       e = launch_step(b->Q, f64, bgk, b->cpt, false, b->d_descs, b->d_work, b->nwork, lat,
-                      b->stream);
+                      b->stream, b->nmwork > 0 ? KernelEvents{} : ev);
     if (e == hipSuccess && b->nmwork > 0)
       e = launch_coef(b->Q, f64, b->coef_k, b->any_ds, b->d_descs, b->d_work + b->nwork,
-                      b->nmwork, lat, b->stream);
+                      b->nmwork, lat, b->stream, b->nwork > 0 ? KernelEvents{} : ev);
     return e;
   };
   if (b->timing) {
@@ -153,10 +155,15 @@ int launch_one(lbm_batch* b) {
     }
     hipEvent_t e0 = next_event(b), e1 = next_event(b);
     if (!e0 || !e1) return LBM_EHIP;
-    if (hipEventRecord(e0, b->stream) != hipSuccess) return LBM_EHIP;
-    if (step() != hipSuccess) return LBM_EHIP;
-    if (hipEventRecord(e1, b->stream) != hipSuccess) return LBM_EHIP;
-  } else if (step() != hipSuccess) {
+    if (b->nwork > 0 && b->nmwork > 0) {
+      // both kernels: events around the pair
+      if (hipEventRecord(e0, b->stream) != hipSuccess) return LBM_EHIP;
+      if (step(KernelEvents{}) != hipSuccess) return LBM_EHIP;
+      if (hipEventRecord(e1, b->stream) != hipSuccess) return LBM_EHIP;
+    } else if (step(KernelEvents{e0, e1}) != hipSuccess) {
+      return LBM_EHIP;
+    }
+  } else if (step(KernelEvents{}) != hipSuccess) {
     return LBM_EHIP;
   }
   if (launch_finalize(f64, b->d_descs, b->d_solves, (int)b->active.size(), 2, b->stream) !=

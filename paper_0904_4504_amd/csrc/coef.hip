@@ -684,27 +684,28 @@ __global__ __launch_bounds__(64 * kCoefWaves) void coef_kernel(const SolveDesc* 
 
 template <class L, typename S, int RB>
 static hipError_t launch_rb(bool ds, const SolveDesc* descs, const WorkItem* work, int nwork,
-                            const KernelLattice& lat, hipStream_t stream) {
+                            const KernelLattice& lat, hipStream_t stream,
+                            const KernelEvents& ev) {
   const CoefConst<S> cc = coef_const<S>(lat);
+  const dim3 grid(nwork), block(64 * kCoefWaves);
   if (ds)
-    hipLaunchKernelGGL((coef_kernel<L, S, RB, true>), dim3(nwork), dim3(64 * kCoefWaves), 0, stream, descs,
-                       work, lat, cc);
+    launch_kernel(coef_kernel<L, S, RB, true>, grid, block, stream, ev, descs, work, lat, cc);
   else
-    hipLaunchKernelGGL((coef_kernel<L, S, RB, false>), dim3(nwork), dim3(64 * kCoefWaves), 0, stream, descs,
-                       work, lat, cc);
+    launch_kernel(coef_kernel<L, S, RB, false>, grid, block, stream, ev, descs, work, lat, cc);
   return hipGetLastError();
 }
 
 template <class L, typename S>
 static hipError_t launch_coef_t(int k, bool ds, const SolveDesc* descs, const WorkItem* work,
-                                int nwork, const KernelLattice& lat, hipStream_t stream) {
+                                int nwork, const KernelLattice& lat, hipStream_t stream,
+                                const KernelEvents& ev) {
   switch (k) {
     case 1:
-      return launch_rb<L, S, 1>(ds, descs, work, nwork, lat, stream);
+      return launch_rb<L, S, 1>(ds, descs, work, nwork, lat, stream, ev);
     case 2:
-      return launch_rb<L, S, 2>(ds, descs, work, nwork, lat, stream);
+      return launch_rb<L, S, 2>(ds, descs, work, nwork, lat, stream, ev);
     case 3:
-      return launch_rb<L, S, 3>(ds, descs, work, nwork, lat, stream);
+      return launch_rb<L, S, 3>(ds, descs, work, nwork, lat, stream, ev);
     default:
       return hipErrorInvalidValue;
   }
@@ -712,13 +713,13 @@ static hipError_t launch_coef_t(int k, bool ds, const SolveDesc* descs, const Wo
 
 hipError_t launch_coef(int Q, bool f64, int k, bool ds, const SolveDesc* descs,
                        const WorkItem* work, int nwork, const KernelLattice& lat,
-                       hipStream_t stream) {
+                       hipStream_t stream, KernelEvents ev) {
   if (nwork <= 0) return hipSuccess;
   if (Q == 9)
-    return f64 ? launch_coef_t<D2Q9, double>(k, ds, descs, work, nwork, lat, stream)
-               : launch_coef_t<D2Q9, float>(k, ds, descs, work, nwork, lat, stream);
-  return f64 ? launch_coef_t<D2Q37, double>(k, ds, descs, work, nwork, lat, stream)
-             : launch_coef_t<D2Q37, float>(k, ds, descs, work, nwork, lat, stream);
+    return f64 ? launch_coef_t<D2Q9, double>(k, ds, descs, work, nwork, lat, stream, ev)
+               : launch_coef_t<D2Q9, float>(k, ds, descs, work, nwork, lat, stream, ev);
+  return f64 ? launch_coef_t<D2Q37, double>(k, ds, descs, work, nwork, lat, stream, ev)
+             : launch_coef_t<D2Q37, float>(k, ds, descs, work, nwork, lat, stream, ev);
 }
 
 }  // namespace lbm

@@ -339,29 +339,30 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __res
 
 template <class L, typename S, bool BGK>
 static hipError_t launch_step_t(int cpt, bool outm, const SolveDesc* descs, const WorkItem* work,
-                                int nwork, const KernelLattice& lat, hipStream_t stream) {
+                                int nwork, const KernelLattice& lat, hipStream_t stream,
+                                const KernelEvents& ev) {
   if (outm) {
     if constexpr (BGK) {
       return hipErrorInvalidValue;
     } else {
       if (cpt != 1) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((step_kernel<L, S, false, kBlock, true>), dim3(nwork), dim3(kBlock), 0,
-                         stream, descs, work, lat);
+      launch_kernel(step_kernel<L, S, false, kBlock, true>, dim3(nwork), dim3(kBlock), stream, ev,
+                    descs, work, lat);
       return hipGetLastError();
     }
   }
   switch (cpt) {
     case 1:
-      hipLaunchKernelGGL((step_kernel<L, S, BGK, kBlock, false>), dim3(nwork), dim3(kBlock), 0,
-                         stream, descs, work, lat);
+      launch_kernel(step_kernel<L, S, BGK, kBlock, false>, dim3(nwork), dim3(kBlock), stream, ev,
+                    descs, work, lat);
       break;
     case 2:
-      hipLaunchKernelGGL((step_kernel<L, S, BGK, 2 * kBlock, false>), dim3(nwork),
-                         dim3(2 * kBlock), 0, stream, descs, work, lat);
+      launch_kernel(step_kernel<L, S, BGK, 2 * kBlock, false>, dim3(nwork), dim3(2 * kBlock),
+                    stream, ev, descs, work, lat);
       break;
     case 4:
-      hipLaunchKernelGGL((step_kernel<L, S, BGK, 4 * kBlock, false>), dim3(nwork),
-                         dim3(4 * kBlock), 0, stream, descs, work, lat);
+      launch_kernel(step_kernel<L, S, BGK, 4 * kBlock, false>, dim3(nwork), dim3(4 * kBlock),
+                    stream, ev, descs, work, lat);
       break;
     default:
       return hipErrorInvalidValue;
@@ -371,20 +372,22 @@ static hipError_t launch_step_t(int cpt, bool outm, const SolveDesc* descs, cons
 
 hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, bool outm, const SolveDesc* descs,
                        const WorkItem* work, int nwork, const KernelLattice& lat,
-                       hipStream_t stream) {
+                       hipStream_t stream, KernelEvents ev) {
   if (nwork <= 0) return hipSuccess;
   if (Q == 9) {
     if (f64)
-      return bgk ? launch_step_t<D2Q9, double, true>(cpt, outm, descs, work, nwork, lat, stream)
-                 : launch_step_t<D2Q9, double, false>(cpt, outm, descs, work, nwork, lat, stream);
-    return bgk ? launch_step_t<D2Q9, float, true>(cpt, outm, descs, work, nwork, lat, stream)
-               : launch_step_t<D2Q9, float, false>(cpt, outm, descs, work, nwork, lat, stream);
+      return bgk ? launch_step_t<D2Q9, double, true>(cpt, outm, descs, work, nwork, lat, stream, ev)
+                 : launch_step_t<D2Q9, double, false>(cpt, outm, descs, work, nwork, lat, stream,
+                                                      ev);
+    return bgk ? launch_step_t<D2Q9, float, true>(cpt, outm, descs, work, nwork, lat, stream, ev)
+               : launch_step_t<D2Q9, float, false>(cpt, outm, descs, work, nwork, lat, stream, ev);
   }
   if (f64)
-    return bgk ? launch_step_t<D2Q37, double, true>(cpt, outm, descs, work, nwork, lat, stream)
-               : launch_step_t<D2Q37, double, false>(cpt, outm, descs, work, nwork, lat, stream);
-  return bgk ? launch_step_t<D2Q37, float, true>(cpt, outm, descs, work, nwork, lat, stream)
-             : launch_step_t<D2Q37, float, false>(cpt, outm, descs, work, nwork, lat, stream);
+    return bgk ? launch_step_t<D2Q37, double, true>(cpt, outm, descs, work, nwork, lat, stream, ev)
+               : launch_step_t<D2Q37, double, false>(cpt, outm, descs, work, nwork, lat, stream,
+                                                     ev);
+  return bgk ? launch_step_t<D2Q37, float, true>(cpt, outm, descs, work, nwork, lat, stream, ev)
+             : launch_step_t<D2Q37, float, false>(cpt, outm, descs, work, nwork, lat, stream, ev);
 }
 
 hipError_t launch_finalize(bool f64, const SolveDesc* descs, const int32_t* solves, int nsolves,

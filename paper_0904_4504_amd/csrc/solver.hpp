@@ -6,6 +6,12 @@
 
 namespace lbm {
 
+// Events a kernel launch records itself at its start and end (the dispatch
+// timestamps, as a profiler's trace sees them); null: none.
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
 constexpr int kCoefTileW = 64;   // coefficient kernel: tile width (one column per lane)
 constexpr int kCoefKMax = 3;     // coefficient kernel: tile variants K = 1..3
