@@ -508,7 +508,10 @@ int create_common(const lbm_params* p, void* stream, void* dev_buf, uint64_t byt
 // One step of a single solver: the population kernel, the population kernel
 // writing coefficients (first step after populations were loaded into a
 // coefficient solver), or the coefficient kernel; then the finalize.
-int step_one(lbm_solver* s) {
+namespace {
+
+// Enqueue one step's launches (no host bookkeeping).
+int launch_one_step(lbm_solver* s) {
   const bool f64 = s->p.storage == LBM_STORE_F64;
   const bool bgk = s->p.collision == LBM_COLL_BGK;
   const int Q = (int)s->p.lattice;
@@ -529,6 +532,41 @@ int step_one(lbm_solver* s) {
   if (e != hipSuccess) return LBM_EHIP;
   if (launch_finalize(f64, s->d_desc, s->d_solves, 1, mode, s->stream) != hipSuccess)
     return LBM_EHIP;
+  return LBM_OK;
+}
+
+// Capture kGraphSteps steps of a solver whose state is in its steady
+// representation (no pending population load).
+bool capture_steps(lbm_solver* s) {
+  if (s->stream == nullptr || s->pop_pending) return false;  // the null stream cannot be captured
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  bool ok = true;
+  for (int k = 0; k < kGraphSteps && ok; ++k) ok = launch_one_step(s) == LBM_OK;
+  if (hipStreamEndCapture(s->stream, &g) != hipSuccess || !ok) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    return false;
+  }
+  hipGraphExec_t ex = nullptr;
+  const bool inst = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipGraphDestroy(g);
+  if (!inst) {
+    (void)hipGetLastError();
+    return false;
+  }
+  s->graph = ex;
+  return true;
+}
+
+}  // namespace
+
+int step_one(lbm_solver* s) {
+  const int rc = launch_one_step(s);
+  if (rc) return rc;
   ++s->steps;
   return LBM_OK;
 }
@@ -602,7 +640,22 @@ int lbm_create_in(const lbm_params* p, void* hip_stream, void* dev_buf, uint64_t
 int lbm_step(lbm_solver* s, int64_t nsteps) {
   if (!s || nsteps < 0) return LBM_EINVAL;
   if (s->steps + nsteps > s->p.max_steps) return LBM_ERANGE;
-  for (int64_t k = 0; k < nsteps; ++k) {
+  int64_t k = 0;
+  // a coefficient solver whose state was loaded as populations converts it
+  // in its first step (another kernel than the steady one)
+  if (s->pop_pending && k < nsteps) {
+    int rc = step_one(s);
+    if (rc) return rc;
+    ++k;
+  }
+  // steady chunks replay one captured graph
+  if (nsteps - k >= kGraphSteps && s->graphs_ok && !s->graph && !capture_steps(s))
+    s->graphs_ok = false;
+  for (; s->graph && k + kGraphSteps <= nsteps; k += kGraphSteps) {
+    if (hipGraphLaunch(s->graph, s->stream) != hipSuccess) return LBM_EHIP;
+    s->steps += kGraphSteps;
+  }
+  for (; k < nsteps; ++k) {
     int rc = step_one(s);
     if (rc) return rc;
   }
@@ -867,6 +920,7 @@ int lbm_set_state(lbm_solver* s, const void* host, uint64_t bytes) {
 int lbm_destroy(lbm_solver* s) {
   if (!s) return LBM_OK;
   int rc = hipStreamSynchronize(s->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+  if (s->graph) (void)hipGraphExecDestroy(s->graph);
   if (s->owned && hipFree(s->base) != hipSuccess) rc = LBM_EHIP;
   delete s;
   return rc;

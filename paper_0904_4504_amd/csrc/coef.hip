@@ -281,7 +281,9 @@ __device__ __forceinline__ lptr<const T> opaque(lptr<const T> p) {
 }
 
 // Raw buffer resource over `bytes` bytes at p (a wave-uniform address):
-// loads at offsets past the end return zero.
+// loads at offsets past the end return zero.  Word 3 = 0x00020000 sets the
+// 32-bit data format (bits 15-18 = 4) with no swizzle or index stride, the
+// untyped-access setting of the gfx9 family.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, uint32_t bytes) {
   const uint64_t v = (uint64_t)p;
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);

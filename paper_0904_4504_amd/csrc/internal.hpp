@@ -63,6 +63,8 @@ struct lbm_solver;
 // One step of a single solver (population, population-to-coefficient or
 // coefficient kernel, then the finalize); defined in api.cpp.
 int step_one(lbm_solver* s);
+// Steps of a single solver captured into one graph.
+constexpr int kGraphSteps = 32;
 
 struct lbm_solver {
   // solver state; host fields mirror the device counters after a sync
@@ -84,5 +86,9 @@ struct lbm_solver {
   int32_t* d_solves = nullptr;
   bool sticky_unstable = false;
   int64_t hist_from = 0;      // first step whose force is in the ring
+  // graph of kGraphSteps steps (captured on first use; the launches read the
+  // step index from the device, so one graph serves every later chunk)
+  hipGraphExec_t graph = nullptr;
+  bool graphs_ok = true;
 };
 

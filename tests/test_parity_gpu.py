@@ -465,7 +465,8 @@ def test_graph_replays_match_eager(P):
     stream = torch.cuda.Stream()
     s = _mix()[0].scaled(64, 40)
     with P.Solver(P.params_from_solve(s), stream=stream) as ref:
-        ref.step(64)
+        for _ in range(64):
+            ref.step(1)   # one step per call: plain launches
         rx, _ = ref.force_history(0, 64)
     with P.Solver(P.params_from_solve(s), stream=stream) as sv:
         b = P.Batch(stream)
@@ -480,6 +481,38 @@ def test_graph_replays_match_eager(P):
             assert np.array_equal(fx, rx[16 * r:16 * (r + 1)]), r
             del junk
         b.close()
+
+
+@pytest.mark.parametrize("repr_", [1, 2], ids=["populations", "coefficients"])
+def test_single_solver_graph_replays_match_eager(P, repr_):
+    """A single solver's step calls of 32 steps or more replay a captured
+    graph: four replays, with eager work and synchronisation between them,
+    each agree bit for bit with one-step calls (plain launches), forces and
+    final state."""
+    import torch
+    stream = torch.cuda.Stream()
+    s = _mix()[0].scaled(4 * 32, 100)
+    v, w, th = P.lattice(s.Q)
+    f0 = _f0(s, w, seed=7, amp=1e-3)
+    with P.Solver(P.params_from_solve(s, representation=repr_), stream=stream) as ref:
+        ref.set_populations(f0)
+        for _ in range(4 * 32):
+            ref.step(1)
+        rx, ry = ref.force_history(0, 4 * 32)
+        rf = ref.get_populations()
+    with P.Solver(P.params_from_solve(s, representation=repr_), stream=stream) as sv:
+        sv.set_populations(f0)
+        sv.step(1)                # the first step after a load runs alone
+        for r in range(4):
+            sv.step(32 if r < 3 else 31)
+            with torch.cuda.stream(stream):
+                junk = torch.ones(1000, device="cuda") * r   # eager work between replays
+            sv.synchronize()
+            lo, n = (1 + 32 * r, 32) if r < 3 else (97, 31)
+            fx, fy = sv.force_history(lo, n)
+            assert np.array_equal(fx, rx[lo:lo + n]) and np.array_equal(fy, ry[lo:lo + n]), r
+            del junk
+        assert np.array_equal(sv.get_populations(), rf)
 
 
 def test_batch_rejects_mismatched_members(P):
