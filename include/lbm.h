@@ -165,9 +165,10 @@ int lbm_create_in(const lbm_params* p, void* hip_stream, void* dev_buf, uint64_t
 
 /* Enqueue nsteps steps on the solver's stream and return without waiting.
  * Calls of 32 steps or more replay a HIP graph of 32 steps that the first
- * such call captures on the stream (not on the null stream, and not while
- * the caller is capturing the stream: then the steps are launched one by
- * one, into the caller's capture).  Results are the same either way.
+ * such call captures on the stream.  On the null stream, or if that first
+ * call finds the stream already being captured by the caller, the solver
+ * launches step by step from then on (into the caller's capture, if any).
+ * Results are the same either way.
  * LBM_ERANGE if the run would pass max_steps (nothing is enqueued). */
 int lbm_step(lbm_solver* s, int64_t nsteps);
 
