@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_0904_4504_amd", "csrc")
 # dominant kernel per device representation: (name, source file, counters file)
 KERNELS = {
-    1: ("lbm::step_kernel<D2Q37, float, false, 256, false>", "kernels.hip",
+    1: ("lbm::step_kernel<D2Q37, float, false, false, 256, false>", "kernels.hip",
         "step_kernel_beam_box_counters.json"),
     2: ("lbm::coef_kernel<D2Q37, float, {rb}, false>", "coef.hip",
         "coef_kernel_beam_box_counters.json"),

@@ -237,10 +237,10 @@ int lbm_destroy(lbm_solver* s);
 /* ------------------------------------------------------------------ batches
  * A batch advances many solvers -- uneven lattices with the same lattice,
  * storage and collision, created on the batch's stream -- with one fused
- * stream-collide launch per step over the tiles of every member and one
- * launch that reduces each member's wall force.  Each member's arithmetic is
- * the same as when it is stepped alone, so its results are bit-identical
- * alone and in any mix.  Members may join and leave between steps
+ * stream-collide launch per step over the tiles of every member of a kind
+ * and one launch that reduces each member's wall force.  Each member runs the
+ * kernel it runs when stepped alone, so its results are bit-identical alone
+ * and in any mix.  Members may join and leave between steps
  * (continuous batching); a member stops when it reaches its max_steps.
  * Member read-out (force history, impedance, populations) goes through the
  * lbm_solver calls above.  The batch never owns or frees its members. */
@@ -254,9 +254,9 @@ int lbm_batch_create(void* hip_stream, lbm_batch** out);
 /* Add / remove a member (between steps).  LBM_EINVAL if the solver's stream,
  * lattice, storage or collision differs from the batch, if two members kept
  * in the same representation differ in `tile`, or on a double add / a remove of a
- * non-member.  A member joins at its own current step.  Members kept as
- * populations and members kept as coefficients are advanced by one launch of
- * each kernel per step. */
+ * non-member.  A member joins at its own current step.  The kinds of member
+ * -- kept as populations or as coefficients, with a bounce-back or a diffuse
+ * (or Maxwell) moving wall -- are advanced by one launch each per step. */
 int lbm_batch_add(lbm_batch* b, lbm_solver* s);
 int lbm_batch_remove(lbm_batch* b, lbm_solver* s);
 

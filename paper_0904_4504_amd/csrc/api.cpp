@@ -515,18 +515,19 @@ int launch_one_step(lbm_solver* s) {
   const bool f64 = s->p.storage == LBM_STORE_F64;
   const bool bgk = s->p.collision == LBM_COLL_BGK;
   const int Q = (int)s->p.lattice;
+  const bool ds = s->p.wall != LBM_WALL_BB;
   int mode = 0;
   hipError_t e;
   if (!s->lay.mom) {
-    e = launch_step(Q, f64, bgk, s->lay.cpt, false, s->d_desc, s->d_work, s->lay.nwork, s->klat,
-                    s->stream);
+    e = launch_step(Q, f64, bgk, ds, s->lay.cpt, false, s->d_desc, s->d_work, s->lay.nwork,
+                    s->klat, s->stream);
   } else if (s->pop_pending) {
-    e = launch_step(Q, f64, false, 1, true, s->d_desc, s->d_work, s->lay.nwork, s->klat,
+    e = launch_step(Q, f64, false, ds, 1, true, s->d_desc, s->d_work, s->lay.nwork, s->klat,
                     s->stream);
     s->pop_pending = false;
   } else {
-    e = launch_coef(Q, f64, s->lay.coef_k, s->p.wall != LBM_WALL_BB, s->d_desc, s->d_mwork,
-                    s->lay.mnwork, s->klat, s->stream);
+    e = launch_coef(Q, f64, s->lay.coef_k, ds, s->d_desc, s->d_mwork, s->lay.mnwork, s->klat,
+                    s->stream);
     mode = 1;
   }
   if (e != hipSuccess) return LBM_EHIP;

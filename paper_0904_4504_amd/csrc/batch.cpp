@@ -26,8 +26,10 @@ struct lbm_batch {
   // current launch set (members that still have steps to run)
   std::vector<lbm_solver*> active;
   bool dirty = true;
-  int nwork = 0, nmwork = 0;  // population-kernel and coefficient-kernel items
-  bool any_ds = false;        // a coefficient member of the launch has a diffuse wall
+  // work items in four consecutive groups, one launch each: population
+  // kernel (bounce-back wall, diffuse wall), coefficient kernel (the same);
+  // every member runs the kernel instantiation it runs alone
+  int ngroup[4] = {0, 0, 0, 0};
   SolveDesc* d_descs = nullptr;
   WorkItem* d_work = nullptr;   // population-kernel items, then coefficient-kernel items
   int32_t* d_solves = nullptr;
@@ -76,24 +78,24 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
   b->active = act;
   b->dirty = false;
   std::vector<SolveDesc> descs;
-  std::vector<WorkItem> work, mwork;
+  std::vector<WorkItem> group[4], work;
   std::vector<int32_t> solves;
-  b->any_ds = false;
   for (size_t i = 0; i < act.size(); ++i) {
-    if (act[i]->lay.mom && act[i]->p.wall != LBM_WALL_BB) b->any_ds = true;
     descs.push_back(act[i]->desc);
     solves.push_back((int32_t)i);
     const Layout& lay = act[i]->lay;
+    std::vector<WorkItem>* g = &group[(lay.mom ? 2 : 0) + (act[i]->p.wall != LBM_WALL_BB)];
     if (lay.mom) {
-      order_tiles(&mwork, (int32_t)i, lay.mntiles, lay.tiles_x);
+      order_tiles(g, (int32_t)i, lay.mntiles, lay.tiles_x);
     } else {
-      order_tiles(&work, (int32_t)i, lay.ntiles,
+      order_tiles(g, (int32_t)i, lay.ntiles,
                   (act[i]->p.nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
     }
   }
-  b->nwork = (int)work.size();
-  b->nmwork = (int)mwork.size();
-  work.insert(work.end(), mwork.begin(), mwork.end());
+  for (int k = 0; k < 4; ++k) {
+    b->ngroup[k] = (int)group[k].size();
+    work.insert(work.end(), group[k].begin(), group[k].end());
+  }
   if (act.empty()) return LBM_OK;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EHIP;
   int rc;
@@ -136,17 +138,26 @@ int collect_timing(lbm_batch* b) {
 int launch_one(lbm_batch* b) {
   const bool f64 = b->storage == LBM_STORE_F64, bgk = b->collision == LBM_COLL_BGK;
   const KernelLattice& lat = b->active[0]->klat;
-  // ev: the launch records its own start and end (the timed kernel is the
-  // only step kernel of the launch set)
+  int nlaunch = 0;
+  for (int k = 0; k < 4; ++k) nlaunch += b->ngroup[k] > 0;
+  // ev: the launch records its own start and end (it is the only step
+  // kernel launch of the launch set)
   auto step = [&](KernelEvents ev) {
-    hipError_t e = hipSuccess;
-    if (b->nwork > 0)
-      e = launch_step(b->Q, f64, bgk, b->cpt, false, b->d_descs, b->d_work, b->nwork, lat,
-                      b->stream, b->nmwork > 0 ? KernelEvents{} : ev);
-    if (e == hipSuccess && b->nmwork > 0)
-      e = launch_coef(b->Q, f64, b->coef_k, b->any_ds, b->d_descs, b->d_work + b->nwork,
-                      b->nmwork, lat, b->stream, b->nwork > 0 ? KernelEvents{} : ev);
-    return e;
+    const KernelEvents own = nlaunch == 1 ? ev : KernelEvents{};
+    const WorkItem* work = b->d_work;
+    for (int k = 0; k < 4; ++k) {
+      const int n = b->ngroup[k];
+      if (n == 0) continue;
+      const bool ds = k & 1;
+      const hipError_t e =
+          k < 2 ? launch_step(b->Q, f64, bgk, ds, b->cpt, false, b->d_descs, work, n, lat,
+                              b->stream, own)
+                : launch_coef(b->Q, f64, b->coef_k, ds, b->d_descs, work, n, lat, b->stream,
+                              own);
+      if (e != hipSuccess) return e;
+      work += n;
+    }
+    return hipSuccess;
   };
   if (b->timing) {
     if (b->ev_used + 2 > 4096) {
@@ -155,8 +166,8 @@ int launch_one(lbm_batch* b) {
     }
     hipEvent_t e0 = next_event(b), e1 = next_event(b);
     if (!e0 || !e1) return LBM_EHIP;
-    if (b->nwork > 0 && b->nmwork > 0) {
-      // both kernels: events around the pair
+    if (nlaunch > 1) {
+      // several launches: events around them
       if (hipEventRecord(e0, b->stream) != hipSuccess) return LBM_EHIP;
       if (step(KernelEvents{}) != hipSuccess) return LBM_EHIP;
       if (hipEventRecord(e1, b->stream) != hipSuccess) return LBM_EHIP;

@@ -11,9 +11,10 @@
 
 namespace lbm {
 
-hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, bool outm, const SolveDesc* descs,
-                       const WorkItem* work, int nwork, const KernelLattice& lat,
-                       hipStream_t stream, KernelEvents ev = {});
+// ds: some solve of the launch has a diffuse-scattering wall.
+hipError_t launch_step(int Q, bool f64, bool bgk, bool ds, int cpt, bool outm,
+                       const SolveDesc* descs, const WorkItem* work, int nwork,
+                       const KernelLattice& lat, hipStream_t stream, KernelEvents ev = {});
 // ds: some solve of the launch has a diffuse-scattering wall.
 hipError_t launch_coef(int Q, bool f64, int k, bool ds, const SolveDesc* descs,
                        const WorkItem* work, int nwork, const KernelLattice& lat,

@@ -43,8 +43,9 @@ namespace lbm {
 // cells of the domain edge or of the body: periodic wrap, bounce-back at the
 // moving wall / body (with the moving-wall term), stationary far wall or
 // rest-equilibrium far field (delta f = 0).  The wall force is computed from
-// the same input state by the finalize kernel.
-template <class L, typename S, int q>
+// the same input state by the finalize kernel.  DSW: the plate's moving wall
+// may be diffuse (else it is bounce-back).
+template <class L, typename S, bool DSW, int q>
 __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__ fin, int x,
                                        int y, double ladd, double wq, double U, double cm,
                                        double theta) {
@@ -70,7 +71,7 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
         // column x - vx at the mirror row), or bounce-back (retrace in y,
         // keep x)
         const int py = -1 - sy;
-        if (d.wall == WALL_DS) {
+        if (DSW && d.wall == WALL_DS) {
           const double e = ds_arrival<vx>(d, U, cm, wq, theta);
           if (d.sigma == 1.0) return (S)e;
           constexpr int qr = reflect_y<L>(q);
@@ -107,7 +108,7 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
 // post-collision state (a0, bx, by, cxx, cxy, cyy) to the coefficient planes
 // instead of the Q populations (regularized collision only; used for the first
 // step after populations were loaded into a solver kept in coefficients).
-template <class L, typename S, bool BGK, bool OUTM>
+template <class L, typename S, bool BGK, bool DSW, bool OUTM>
 __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restrict__ fin,
                                             S* __restrict__ fout, int64_t n, int c,
                                             const KernelLattice& lat) {
@@ -136,7 +137,7 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
     const double ladd = d.ladd_scale * U;
     // diffuse wall: deviation of the mass crossing the wall in column x
     double cm = 0.0;
-    if (d.wall == WALL_DS && d.geom == GEOM_PLATE && y < R)
+    if (DSW && d.wall == WALL_DS && d.geom == GEOM_PLATE && y < R)
       static_for<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (L::vy[q] < 0)
@@ -144,7 +145,7 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
       });
     static_for<0, Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      f[q] = pull_edge<L, S, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], U, cm, lat.theta);
+      f[q] = pull_edge<L, S, DSW, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], U, cm, lat.theta);
     });
   } else {
     static_for<0, Q>([&](auto qc) { f[decltype(qc)::value] = S(0); });
@@ -223,8 +224,9 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
 }
 
 // One workgroup of BS threads per tile of BS consecutive cells (row-major),
-// one cell per thread.
-template <class L, typename S, bool BGK, int BS, bool OUTM>
+// one cell per thread.  The diffuse wall is a separate instantiation (DSW), so
+// that the bounce-back kernel carries none of its code and registers.
+template <class L, typename S, bool BGK, bool DSW, int BS, bool OUTM>
 __global__ __launch_bounds__(BS) void step_kernel(const SolveDesc* __restrict__ descs,
                                                   const WorkItem* __restrict__ work,
                                                   KernelLattice lat) {
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(BS) void step_kernel(const SolveDesc* __restrict__ 
   const int64_t n = d.state->step;
   const S* __restrict__ fin = static_cast<const S*>(d.buf[n & 1]);
   S* __restrict__ fout = static_cast<S*>(OUTM ? d.mbuf[(n & 1) ^ 1] : d.buf[(n & 1) ^ 1]);
-  update_cell<L, S, BGK, OUTM>(d, fin, fout, n, wi.tile * BS + (int)threadIdx.x, lat);
+  update_cell<L, S, BGK, DSW, OUTM>(d, fin, fout, n, wi.tile * BS + (int)threadIdx.x, lat);
 }
 
 // One workgroup per solve.  Wall force of step n by momentum exchange (Sec.
@@ -337,32 +339,22 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const SolveDesc* __res
   finalize_solve<S>(descs[solves[blockIdx.x]], mode);
 }
 
-template <class L, typename S, bool BGK>
-static hipError_t launch_step_t(int cpt, bool outm, const SolveDesc* descs, const WorkItem* work,
-                                int nwork, const KernelLattice& lat, hipStream_t stream,
+template <class L, typename S, bool BGK, bool DSW>
+static hipError_t launch_step_t(int cpt, const SolveDesc* descs, const WorkItem* work, int nwork,
+                                const KernelLattice& lat, hipStream_t stream,
                                 const KernelEvents& ev) {
-  if (outm) {
-    if constexpr (BGK) {
-      return hipErrorInvalidValue;
-    } else {
-      if (cpt != 1) return hipErrorInvalidValue;
-      launch_kernel(step_kernel<L, S, false, kBlock, true>, dim3(nwork), dim3(kBlock), stream, ev,
-                    descs, work, lat);
-      return hipGetLastError();
-    }
-  }
   switch (cpt) {
     case 1:
-      launch_kernel(step_kernel<L, S, BGK, kBlock, false>, dim3(nwork), dim3(kBlock), stream, ev,
-                    descs, work, lat);
+      launch_kernel(step_kernel<L, S, BGK, DSW, kBlock, false>, dim3(nwork), dim3(kBlock), stream,
+                    ev, descs, work, lat);
       break;
     case 2:
-      launch_kernel(step_kernel<L, S, BGK, 2 * kBlock, false>, dim3(nwork), dim3(2 * kBlock),
-                    stream, ev, descs, work, lat);
+      launch_kernel(step_kernel<L, S, BGK, DSW, 2 * kBlock, false>, dim3(nwork),
+                    dim3(2 * kBlock), stream, ev, descs, work, lat);
       break;
     case 4:
-      launch_kernel(step_kernel<L, S, BGK, 4 * kBlock, false>, dim3(nwork), dim3(4 * kBlock),
-                    stream, ev, descs, work, lat);
+      launch_kernel(step_kernel<L, S, BGK, DSW, 4 * kBlock, false>, dim3(nwork),
+                    dim3(4 * kBlock), stream, ev, descs, work, lat);
       break;
     default:
       return hipErrorInvalidValue;
@@ -370,24 +362,37 @@ static hipError_t launch_step_t(int cpt, bool outm, const SolveDesc* descs, cons
   return hipGetLastError();
 }
 
-hipError_t launch_step(int Q, bool f64, bool bgk, int cpt, bool outm, const SolveDesc* descs,
-                       const WorkItem* work, int nwork, const KernelLattice& lat,
-                       hipStream_t stream, KernelEvents ev) {
-  if (nwork <= 0) return hipSuccess;
-  if (Q == 9) {
-    if (f64)
-      return bgk ? launch_step_t<D2Q9, double, true>(cpt, outm, descs, work, nwork, lat, stream, ev)
-                 : launch_step_t<D2Q9, double, false>(cpt, outm, descs, work, nwork, lat, stream,
-                                                      ev);
-    return bgk ? launch_step_t<D2Q9, float, true>(cpt, outm, descs, work, nwork, lat, stream, ev)
-               : launch_step_t<D2Q9, float, false>(cpt, outm, descs, work, nwork, lat, stream, ev);
+template <class L, typename S>
+static hipError_t launch_step_l(bool bgk, bool ds, int cpt, bool outm, const SolveDesc* descs,
+                                const WorkItem* work, int nwork, const KernelLattice& lat,
+                                hipStream_t stream, const KernelEvents& ev) {
+  if (outm) {
+    // one step of a solver kept in coefficients: any wall
+    if (bgk || cpt != 1) return hipErrorInvalidValue;
+    launch_kernel(step_kernel<L, S, false, true, kBlock, true>, dim3(nwork), dim3(kBlock), stream,
+                  ev, descs, work, lat);
+    return hipGetLastError();
   }
-  if (f64)
-    return bgk ? launch_step_t<D2Q37, double, true>(cpt, outm, descs, work, nwork, lat, stream, ev)
-               : launch_step_t<D2Q37, double, false>(cpt, outm, descs, work, nwork, lat, stream,
-                                                     ev);
-  return bgk ? launch_step_t<D2Q37, float, true>(cpt, outm, descs, work, nwork, lat, stream, ev)
-             : launch_step_t<D2Q37, float, false>(cpt, outm, descs, work, nwork, lat, stream, ev);
+  if (bgk)
+    return ds ? launch_step_t<L, S, true, true>(cpt, descs, work, nwork, lat, stream, ev)
+              : launch_step_t<L, S, true, false>(cpt, descs, work, nwork, lat, stream, ev);
+  return ds ? launch_step_t<L, S, false, true>(cpt, descs, work, nwork, lat, stream, ev)
+            : launch_step_t<L, S, false, false>(cpt, descs, work, nwork, lat, stream, ev);
+}
+
+hipError_t launch_step(int Q, bool f64, bool bgk, bool ds, int cpt, bool outm,
+                       const SolveDesc* descs, const WorkItem* work, int nwork,
+                       const KernelLattice& lat, hipStream_t stream, KernelEvents ev) {
+  if (nwork <= 0) return hipSuccess;
+  if (Q == 9)
+    return f64 ? launch_step_l<D2Q9, double>(bgk, ds, cpt, outm, descs, work, nwork, lat, stream,
+                                             ev)
+               : launch_step_l<D2Q9, float>(bgk, ds, cpt, outm, descs, work, nwork, lat, stream,
+                                            ev);
+  return f64 ? launch_step_l<D2Q37, double>(bgk, ds, cpt, outm, descs, work, nwork, lat, stream,
+                                            ev)
+             : launch_step_l<D2Q37, float>(bgk, ds, cpt, outm, descs, work, nwork, lat, stream,
+                                           ev);
 }
 
 hipError_t launch_finalize(bool f64, const SolveDesc* descs, const int32_t* solves, int nsolves,

@@ -286,7 +286,7 @@ class Solver:
 
 
 class Batch:
-    """Several solvers advanced by one fused launch per step (lbm_batch_*).
+    """Several solvers advanced by one fused launch per kind of member and step (lbm_batch_*).
     Members must share the batch's stream, lattice, storage and collision."""
 
     def __init__(self, stream=None):

@@ -458,6 +458,41 @@ def test_batch_alone_equals_mix(P, graphs):
         sv.close()
 
 
+def test_batch_alone_equals_mix_with_diffuse_walls(P):
+    """Diffuse and Maxwell walls beside bounce-back members, in both device
+    representations: the launch then runs the kernels that carry the diffuse
+    wall, and every member's forces and populations are still bit-identical
+    to the same solve stepped alone."""
+    import torch
+    stream = torch.cuda.Stream()
+    om = 2 * math.pi / 40
+    solves = [
+        W.Solve(Q=37, geometry=W.PLATE, far=W.FAR_WALL, nx=4, ny=300, tau=3.0, omega=om,
+                nsteps=45, window_first=5, window_count=40, wall="ds", name="plate_ds"),
+        W.Solve(Q=37, geometry=W.PLATE, far=W.FAR_EQ, nx=4, ny=200, tau=0.7, omega=om,
+                nsteps=45, window_first=5, window_count=40, name="plate_bb"),
+        W.Solve(Q=37, geometry=W.PLATE, far=W.FAR_EQ, nx=130, ny=50, tau=0.55, omega=om,
+                nsteps=45, window_first=5, window_count=40, wall="maxwell",
+                accommodation=0.6, name="wide_maxwell"),
+        W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=90, ny=70, tau=0.9, omega=om,
+                box=(30, 25, 20, 12), nsteps=45, window_first=5, window_count=40, name="box"),
+    ]
+    ref = [_alone(P, s, stream) for s in solves]
+    svs = [P.Solver(P.params_from_solve(s), stream=stream) for s in solves]
+    b = P.Batch(stream)
+    for sv in svs:
+        b.add(sv)
+    b.step(45)
+    b.synchronize()
+    for s, sv, (rx, ry, rf) in zip(solves, svs, ref):
+        fx, fy = sv.force_history(0, s.nsteps)
+        assert np.array_equal(fx, rx) and np.array_equal(fy, ry), s.name
+        assert np.array_equal(sv.get_populations(), rf), s.name
+    b.close()
+    for sv in svs:
+        sv.close()
+
+
 def test_graph_replays_match_eager(P):
     """Replays of the captured graph, with eager work and synchronisation
     between them, each agree with plain launches."""
