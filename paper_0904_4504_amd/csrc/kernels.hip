@@ -104,6 +104,107 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
   return fin[q * qs + sy * ys + sx];
 }
 
+// Geometry of a solve for the boundary path, read once per cell (so that the
+// per-population selects below work on registers).
+struct EdgeGeom {
+  int nx, ny, bx0, bx1, by0, by1;
+  bool far_eq;
+  int64_t qs, ys;
+};
+
+__device__ __forceinline__ EdgeGeom edge_geom(const SolveDesc& d) {
+  return EdgeGeom{d.nx, d.ny, d.bx0, d.bx1, d.by0, d.by1, d.far == FAR_EQ, d.qs, d.ys};
+}
+
+// A zero of either storage precision, read by arrivals from the far field.
+__device__ const double kZeroWord = 0.0;
+
+// Moments (delta rho, jx, jy, Pxx, Pxy, Pyy) of the moving-wall terms of a
+// cell's bounce-back arrivals.
+template <typename S>
+struct WallMom {
+  S v[6];
+};
+
+// The pull of pull_edge with bounce-back walls only (no diffuse wall), for
+// geometry G, without branches per lane: the source plane, row and column
+// are selected and an arrival of zero (the far field) reads kZeroWord, so a
+// wavefront issues its Q loads back to back.  The moving-wall term of an
+// arrival, 2 w_i rho0 (v_i.U_w)/theta, is returned in `term` (-0 where there
+// is none, so that adding it changes nothing).
+template <class L, typename S, int G, int q>
+__device__ __forceinline__ S pull_edge_bb(const EdgeGeom& g, const S* __restrict__ fin, int x,
+                                          int y, double ladd, double wq, S& term) {
+  constexpr int vx = L::vx[q], vy = L::vy[q];
+  constexpr int o = opposite<L>(q);
+  const int sx = x - vx, sy = y - vy;
+  int pl = q, px = sx, py = sy;
+  bool zero = false, moving = false;
+  if constexpr (G == GEOM_BOX) {
+    // outside the domain: rest-equilibrium far field; inside the body: the
+    // mirror cell of the link (per axis, through the face plane when the
+    // arrival lies outside the body's range on that axis)
+    zero = sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny;
+    moving = sx >= g.bx0 && sx < g.bx1 && sy >= g.by0 && sy < g.by1;
+    const int mx = x < g.bx0 ? 2 * g.bx0 - 1 - sx : (x >= g.bx1 ? 2 * g.bx1 - 1 - sx : x);
+    const int my = y < g.by0 ? 2 * g.by0 - 1 - sy : (y >= g.by1 ? 2 * g.by1 - 1 - sy : y);
+    pl = moving ? o : pl;
+    px = moving ? mx : px;
+    py = moving ? my : py;
+  } else {
+    px += px < 0 ? g.nx : 0;
+    px -= px >= g.nx ? g.nx : 0;
+    if constexpr (G == GEOM_PERIODIC) {
+      py += py < 0 ? g.ny : 0;
+      py -= py >= g.ny ? g.ny : 0;
+    } else {
+      if constexpr (vy > 0) {
+        // moving wall at y = -1/2: retrace in y, keep x
+        moving = sy < 0;
+        pl = moving ? o : pl;
+        px = moving ? x : px;
+        py = moving ? -1 - sy : py;
+      }
+      if constexpr (vy < 0) {
+        // stationary wall at y = ny - 1/2, or the rest-equilibrium far field
+        const bool far = sy >= g.ny;
+        zero = far && g.far_eq;
+        pl = far ? o : pl;
+        px = far ? x : px;
+        py = far ? 2 * g.ny - 1 - sy : py;
+      }
+    }
+  }
+  term = moving ? (S)(wq * vx * ladd) : S(-0.0);
+  const S* src = zero ? reinterpret_cast<const S*>(&kZeroWord) : fin + (pl * g.qs + py * g.ys + px);
+  return *src;
+}
+
+// All Q pulls of a cell through pull_edge_bb for geometry G.  Plain BGK needs
+// every arrival itself (population plus wall term); the regularized
+// collision only their moments, so the wall terms go to `wall` instead.
+template <class L, typename S, bool BGK, int G>
+__device__ __forceinline__ void pull_cell_bb(S (&f)[L::Q], WallMom<S>& wall, const EdgeGeom& g,
+                                             const S* __restrict__ fin, int x, int y,
+                                             double ladd, const KernelLattice& lat) {
+  static_for<0, L::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int vx = L::vx[q], vy = L::vy[q];
+    S term;
+    f[q] = pull_edge_bb<L, S, G, q>(g, fin, x, y, ladd, lat.w[L::orbit[q]], term);
+    if constexpr (BGK) {
+      f[q] += term;
+    } else if constexpr (G == GEOM_BOX || (G == GEOM_PLATE && vy > 0)) {
+      wall.v[0] += term;
+      if constexpr (vx != 0) wall.v[1] += S(vx) * term;
+      if constexpr (vy != 0) wall.v[2] += S(vy) * term;
+      if constexpr (vx != 0) wall.v[3] += S(vx * vx) * term;
+      if constexpr (vx * vy != 0) wall.v[4] += S(vx * vy) * term;
+      if constexpr (vy != 0) wall.v[5] += S(vy * vy) * term;
+    }
+  });
+}
+
 // Update of one cell: pull, moments, collision, store.  OUTM stores the six H2 coefficients of the
 // post-collision state (a0, bx, by, cxx, cxy, cyy) to the coefficient planes
 // instead of the Q populations (regularized collision only; used for the first
@@ -125,9 +226,15 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
                                        y < d.by1 + R);
   const bool fluid = active && !solid;
   const int64_t idx = y * ys + x;
+  // With bounce-back walls a wavefront that has a cell near an edge or the
+  // body pulls every cell through the boundary path (which also covers
+  // interior cells): one pass of loads, no divergence.
+  bool edge = fluid && !interior;
+  if constexpr (!DSW) edge = __any(edge);
 
   S f[Q];
-  if (fluid && interior) {
+  WallMom<S> wall{{S(0), S(0), S(0), S(0), S(0), S(0)}};
+  if (fluid && !edge) {
     static_for<0, Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
       f[q] = fin[q * qs + idx - (L::vy[q] * ys + L::vx[q])];
@@ -143,10 +250,20 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
         if constexpr (L::vy[q] < 0)
           for (int r = 0; r < -L::vy[q]; ++r) cm += (double)fin[q * qs + r * ys + x];
       });
-    static_for<0, Q>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      f[q] = pull_edge<L, S, DSW, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], U, cm, lat.theta);
-    });
+    if constexpr (DSW) {
+      static_for<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        f[q] = pull_edge<L, S, DSW, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], U, cm, lat.theta);
+      });
+    } else {
+      const EdgeGeom g = edge_geom(d);
+      if (d.geom == GEOM_BOX)
+        pull_cell_bb<L, S, BGK, GEOM_BOX>(f, wall, g, fin, x, y, ladd, lat);
+      else if (d.geom == GEOM_PERIODIC)
+        pull_cell_bb<L, S, BGK, GEOM_PERIODIC>(f, wall, g, fin, x, y, ladd, lat);
+      else
+        pull_cell_bb<L, S, BGK, GEOM_PLATE>(f, wall, g, fin, x, y, ladd, lat);
+    }
   } else {
     static_for<0, Q>([&](auto qc) { f[decltype(qc)::value] = S(0); });
   }
@@ -164,6 +281,14 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
     if constexpr (vx * vy != 0) pxy += S(vx * vy) * v;
     if constexpr (vy != 0) pyy += S(vy * vy) * v;
   });
+  if constexpr (!BGK && !DSW) {
+    drho += wall.v[0];
+    jx += wall.v[1];
+    jy += wall.v[2];
+    pxx += wall.v[3];
+    pxy += wall.v[4];
+    pyy += wall.v[5];
+  }
 
   const S th = (S)lat.theta;
   const S inv_th = (S)(1.0 / lat.theta);
