@@ -116,6 +116,10 @@ __device__ __forceinline__ EdgeGeom edge_geom(const SolveDesc& d) {
   return EdgeGeom{d.nx, d.ny, d.bx0, d.bx1, d.by0, d.by1, d.far == FAR_EQ, d.qs, d.ys};
 }
 
+// Boundary path of a box-geometry wavefront away from the body: only the
+// domain edges (the rest-equilibrium far field) are in reach.
+constexpr int kBoxOpen = 3;
+
 // A zero of either storage precision, read by arrivals from the far field.
 __device__ const double kZeroWord = 0.0;
 
@@ -134,10 +138,17 @@ struct WallMom {
 // is none, so that adding it changes nothing).
 template <class L, typename S, int G, int q>
 __device__ __forceinline__ S pull_edge_bb(const EdgeGeom& g, const S* __restrict__ fin, int x,
-                                          int y, double ladd, double wq, S& term) {
+                                          int y, int64_t idx, double ladd, double wq, S& term) {
   constexpr int vx = L::vx[q], vy = L::vy[q];
   constexpr int o = opposite<L>(q);
   const int sx = x - vx, sy = y - vy;
+  if constexpr (G == kBoxOpen) {
+    const bool zero = sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny;
+    term = S(-0.0);
+    const S* src = zero ? reinterpret_cast<const S*>(&kZeroWord)
+                        : fin + (q * g.qs + idx - (vy * g.ys + vx));
+    return *src;
+  }
   int pl = q, px = sx, py = sy;
   bool zero = false, moving = false;
   if constexpr (G == GEOM_BOX) {
@@ -185,13 +196,13 @@ __device__ __forceinline__ S pull_edge_bb(const EdgeGeom& g, const S* __restrict
 // collision only their moments, so the wall terms go to `wall` instead.
 template <class L, typename S, bool BGK, int G>
 __device__ __forceinline__ void pull_cell_bb(S (&f)[L::Q], WallMom<S>& wall, const EdgeGeom& g,
-                                             const S* __restrict__ fin, int x, int y,
+                                             const S* __restrict__ fin, int x, int y, int64_t idx,
                                              double ladd, const KernelLattice& lat) {
   static_for<0, L::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int vx = L::vx[q], vy = L::vy[q];
     S term;
-    f[q] = pull_edge_bb<L, S, G, q>(g, fin, x, y, ladd, lat.w[L::orbit[q]], term);
+    f[q] = pull_edge_bb<L, S, G, q>(g, fin, x, y, idx, ladd, lat.w[L::orbit[q]], term);
     if constexpr (BGK) {
       f[q] += term;
     } else if constexpr (G == GEOM_BOX || (G == GEOM_PLATE && vy > 0)) {
@@ -257,12 +268,16 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
       });
     } else {
       const EdgeGeom g = edge_geom(d);
-      if (d.geom == GEOM_BOX)
-        pull_cell_bb<L, S, BGK, GEOM_BOX>(f, wall, g, fin, x, y, ladd, lat);
-      else if (d.geom == GEOM_PERIODIC)
-        pull_cell_bb<L, S, BGK, GEOM_PERIODIC>(f, wall, g, fin, x, y, ladd, lat);
-      else
-        pull_cell_bb<L, S, BGK, GEOM_PLATE>(f, wall, g, fin, x, y, ladd, lat);
+      if (d.geom == GEOM_BOX) {
+        if (__any(x >= g.bx0 - R && x < g.bx1 + R && y >= g.by0 - R && y < g.by1 + R))
+          pull_cell_bb<L, S, BGK, GEOM_BOX>(f, wall, g, fin, x, y, idx, ladd, lat);
+        else
+          pull_cell_bb<L, S, BGK, kBoxOpen>(f, wall, g, fin, x, y, idx, ladd, lat);
+      } else if (d.geom == GEOM_PERIODIC) {
+        pull_cell_bb<L, S, BGK, GEOM_PERIODIC>(f, wall, g, fin, x, y, idx, ladd, lat);
+      } else {
+        pull_cell_bb<L, S, BGK, GEOM_PLATE>(f, wall, g, fin, x, y, idx, ladd, lat);
+      }
     }
   } else {
     static_for<0, Q>([&](auto qc) { f[decltype(qc)::value] = S(0); });
