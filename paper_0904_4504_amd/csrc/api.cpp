@@ -36,6 +36,48 @@ void order_tiles(std::vector<WorkItem>* out, int32_t solve, int32_t ntiles, int3
       }
 }
 
+// Coefficient-kernel tiles (of a solve with this layout) that hold a cell
+// with a wall link: the band of R cells around the body, the plate's wall rows
+// (the same band the kernel tests per wavefront).
+std::vector<char> coef_wall_tiles(const lbm_params* p, const Layout& lay, int R) {
+  std::vector<char> wall((size_t)lay.mntiles, 0);
+  int wx0 = 0, wx1 = p->nx, wy0 = 0, wy1 = 0;
+  bool far_band = false;
+  if (p->geometry == LBM_GEOM_BOX) {
+    wx0 = p->box_x0 - R;
+    wx1 = p->box_x0 + p->box_lx + R;
+    wy0 = p->box_y0 - R;
+    wy1 = p->box_y0 + p->box_ly + R;
+  } else if (p->geometry == LBM_GEOM_PLATE) {
+    wy1 = R;
+    far_band = p->far == LBM_FAR_WALL;
+  }
+  const int th = coef_tile_rows(lay.coef_k);
+  for (int32_t t = 0; t < lay.mntiles; ++t) {
+    const int x0 = (t % lay.tiles_x) * kCoefTileW, y0 = (t / lay.tiles_x) * th;
+    wall[t] = (x0 < wx1 && x0 + kCoefTileW > wx0 && y0 < wy1 && y0 + th > wy0) ||
+              (far_band && y0 + th > p->ny - R);
+  }
+  return wall;
+}
+
+void order_coef_tiles(std::vector<WorkItem>* front, std::vector<WorkItem>* rest, int32_t solve,
+                      const std::vector<char>& wall, int32_t ntiles, int32_t span) {
+  for (int32_t t = 0; t < ntiles; ++t)
+    if (wall[t]) front->push_back(WorkItem{solve, t});
+  const size_t from = rest->size();
+  order_tiles(rest, solve, ntiles, span);
+  for (size_t i = from; i < rest->size(); ++i) {
+    WorkItem& w = (*rest)[i];
+    if (w.tile >= 0 && wall[w.tile]) w.tile = -1;
+  }
+}
+
+void join_front(std::vector<WorkItem>* front, const std::vector<WorkItem>& rest) {
+  while (front->size() % 8) front->push_back(WorkItem{0, -1});
+  front->insert(front->end(), rest.begin(), rest.end());
+}
+
 // Work-list length order_tiles produces for one solve starting aligned.
 int64_t ordered_length(int64_t ntiles, int64_t span) {
   span = std::max<int64_t>(1, span);
@@ -313,7 +355,9 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
                                                         lay->cells_per_tile);
   lay->off_work = take(sizeof(WorkItem) * (uint64_t)lay->nwork);
   if (lay->mom) {
-    lay->mnwork = (int32_t)ordered_length(lay->mntiles, lay->tiles_x);
+    int64_t nwall = 0;
+    for (char w : coef_wall_tiles(p, *lay, L.R)) nwall += w;
+    lay->mnwork = (int32_t)((nwall + 7) / 8 * 8 + ordered_length(lay->mntiles, lay->tiles_x));
     lay->off_mwork = take(sizeof(WorkItem) * (uint64_t)lay->mnwork);
   }
   lay->off_solves = take(sizeof(int32_t));
@@ -406,7 +450,13 @@ int init_solver(lbm_solver* s) {
 
   std::vector<WorkItem> work, mwork;
   order_tiles(&work, 0, lay.ntiles, (p->nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
-  if (lay.mom) order_tiles(&mwork, 0, lay.mntiles, lay.tiles_x);
+  if (lay.mom) {
+    std::vector<WorkItem> rest;
+    order_coef_tiles(&mwork, &rest, 0, coef_wall_tiles(p, lay, s->lat.R), lay.mntiles,
+                     lay.tiles_x);
+    join_front(&mwork, rest);
+    if ((int32_t)mwork.size() != lay.mnwork) return LBM_EINVAL;
+  }
   std::vector<Drive> drive((size_t)p->max_steps);
   for (int64_t n = 0; n < p->max_steps; ++n) {
     const double arg = p->omega * ((double)n + 0.5);

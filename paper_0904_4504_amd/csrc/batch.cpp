@@ -78,21 +78,28 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
   b->active = act;
   b->dirty = false;
   std::vector<SolveDesc> descs;
-  std::vector<WorkItem> group[4], work;
+  // coefficient groups: every member's wall tiles first (they are the slowest
+  // tiles of the launch), then the rest
+  std::vector<WorkItem> group[4], front[4], work;
   std::vector<int32_t> solves;
   for (size_t i = 0; i < act.size(); ++i) {
     descs.push_back(act[i]->desc);
     solves.push_back((int32_t)i);
     const Layout& lay = act[i]->lay;
-    std::vector<WorkItem>* g = &group[(lay.mom ? 2 : 0) + (act[i]->p.wall != LBM_WALL_BB)];
+    const int k = (lay.mom ? 2 : 0) + (act[i]->p.wall != LBM_WALL_BB);
     if (lay.mom) {
-      order_tiles(g, (int32_t)i, lay.mntiles, lay.tiles_x);
+      order_coef_tiles(&front[k], &group[k], (int32_t)i,
+                       coef_wall_tiles(&act[i]->p, lay, act[i]->lat.R), lay.mntiles, lay.tiles_x);
     } else {
-      order_tiles(g, (int32_t)i, lay.ntiles,
+      order_tiles(&group[k], (int32_t)i, lay.ntiles,
                   (act[i]->p.nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
     }
   }
   for (int k = 0; k < 4; ++k) {
+    if (!front[k].empty()) {
+      join_front(&front[k], group[k]);
+      group[k].swap(front[k]);
+    }
     b->ngroup[k] = (int)group[k].size();
     work.insert(work.end(), group[k].begin(), group[k].end());
   }

@@ -57,6 +57,15 @@ struct Layout {
 // Append the tiles of one solve to a launch work list in XCD-aware order
 // (rows of `span` tiles dealt to the 8 XCDs in turn).
 void order_tiles(std::vector<WorkItem>* out, int32_t solve, int32_t ntiles, int32_t span);
+// Coefficient-kernel tiles of a solve with a wall link (mask over its tiles).
+std::vector<char> coef_wall_tiles(const lbm_params* p, const Layout& lay, int R);
+// The tiles of one coefficient solve: its wall tiles to `front` (they are the
+// slowest of a launch, so they start first), the rest to `rest` in the order
+// of order_tiles with the wall tiles made no-ops (keeping its XCD structure).
+void order_coef_tiles(std::vector<WorkItem>* front, std::vector<WorkItem>* rest, int32_t solve,
+                      const std::vector<char>& wall, int32_t ntiles, int32_t span);
+// front, padded with no-ops to a multiple of 8 items, then rest.
+void join_front(std::vector<WorkItem>* front, const std::vector<WorkItem>& rest);
 
 }  // namespace lbm
 
