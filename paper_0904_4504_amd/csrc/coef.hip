@@ -117,6 +117,22 @@ __device__ __forceinline__ gptr<T> at(gptr<T> p, uint32_t off) {
   return (gptr<T>)((__attribute__((address_space(1))) char*)p + off);
 }
 
+// Two coefficients of a cell: (a0, bx), (by, cxx) or (cxy, cyy).
+template <typename S>
+using Pair = S __attribute__((ext_vector_type(2)));
+
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+
+// The same LDS address, opaque to the compiler: reads relative to it use
+// their small constant offsets directly instead of a new base register each.
+template <typename T>
+__device__ __forceinline__ lptr<const T> opaque(lptr<const T> p) {
+  uint32_t a = (uint32_t)(uintptr_t)p;
+  asm volatile("" : "+v"(a));
+  return (lptr<const T>)(uintptr_t)a;
+}
+
 // Six running moment sums of one output row: delta rho, jx, jy, Pxx, Pxy, Pyy.
 template <typename S>
 struct Mom {
@@ -147,14 +163,22 @@ constexpr bool source_used(int vx, int iy) {
 
 // Bounce-back contributions of the wall links of fluid cell (x, y): each link
 // population arrived as zero from the stream; add f_opp(x_p) (+ the
-// moving-wall term) and its moments.
+// moving-wall term) and its moments.  Every cell a link reads (the mirror
+// cell x_p, the diffuse wall's specular source and its crossing rows) lies
+// within R - 1 cells of (x, y) along each axis, so inside the staged tile:
+// the reads come from LDS (C, staged region starting at cell (ox, oy), rows
+// of HW cells), not from global memory.
 template <class L, typename S, bool DSW>
-__device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<const S> min,
-                                                      int x, int y, S ladd, double U,
-                                                      const KernelLattice& lat,
-                                                      const CoefConst<S>& cc) {
-  const int64_t ks = d.mks;
-  const int ys = (int)d.mys;
+__device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, const Pair<S>* C,
+                                            int HW, int ox, int oy, int x, int y, S ladd,
+                                            double U, const KernelLattice& lat,
+                                            const CoefConst<S>& cc) {
+  const lptr<const Pair<S>> T = (lptr<const Pair<S>>)C;
+  // coefficient k (a0, bx, by, cxx, cxy, cyy) of the cell at (cx, cy)
+  auto coef = [&](int cx, int cy, int k) __attribute__((always_inline)) -> S {
+    const Pair<S> p = T[(3 * (cy - oy) + (k >> 1)) * HW + (cx - ox)];
+    return (k & 1) ? p.y : p.x;
+  };
   const bool is_box = d.geom == GEOM_BOX;
   // diffuse wall: deviation of the mass crossing the wall in column x, from
   // the coefficients of rows 0 .. R-1 (population q at row r crosses when
@@ -163,9 +187,8 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<c
   if (DSW && d.wall == WALL_DS && d.geom == GEOM_PLATE && y < L::R) {
     static_for<0, L::R>([&](auto rc) __attribute__((always_inline)) {
       constexpr int r = decltype(rc)::value;
-      const int g = r * ys + x;
-      const double c0 = min[g], c1 = min[ks + g], c2 = min[2 * ks + g], c3 = min[3 * ks + g],
-                   c4 = min[4 * ks + g], c5 = min[5 * ks + g];
+      const double c0 = coef(x, r, 0), c1 = coef(x, r, 1), c2 = coef(x, r, 2),
+                   c3 = coef(x, r, 3), c4 = coef(x, r, 4), c5 = coef(x, r, 5);
       static_for<0, L::Q>([&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
         constexpr int vx = L::vx[q], vy = L::vy[q];
@@ -211,26 +234,24 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, gptr<c
         double e = ds_arrival<vx>(d, U, cm, lat.w[L::orbit[q]], lat.theta);
         if (d.sigma != 1.0) {
           // specular share: the population of (vx, -vy) that crossed the
-          // wall from column x - vx at the mirror row
-          int sxw = x - vx;
-          sxw += sxw < 0 ? d.nx : 0;
-          sxw -= sxw >= d.nx ? d.nx : 0;
-          const int g = py * ys + sxw;
-          double p = min[g];
-          if constexpr (vx != 0) p += double(vx) * min[ks + g] + double(vx * vx) * min[3 * ks + g];
+          // wall from column x - vx at the mirror row (the staged halo holds
+          // the periodic image of a wrapped column)
+          const int sxw = x - vx;
+          double p = coef(sxw, py, 0);
+          if constexpr (vx != 0)
+            p += double(vx) * coef(sxw, py, 1) + double(vx * vx) * coef(sxw, py, 3);
           if constexpr (vy != 0)
-            p += double(-vy) * min[2 * ks + g] + double(vy * vy) * min[5 * ks + g];
-          if constexpr (vx * vy != 0) p += double(-vx * vy) * min[4 * ks + g];
+            p += double(-vy) * coef(sxw, py, 2) + double(vy * vy) * coef(sxw, py, 5);
+          if constexpr (vx * vy != 0) p += double(-vx * vy) * coef(sxw, py, 4);
           e = d.sigma * e + (1.0 - d.sigma) * lat.w[L::orbit[q]] * p;
         }
         f = (S)e;
       } else {
-        const int g = py * ys + px;
         // population of -v at the mirror cell
-        S p = min[g];
-        if constexpr (vx != 0) p += S(-vx) * min[ks + g] + S(vx * vx) * min[3 * ks + g];
-        if constexpr (vy != 0) p += S(-vy) * min[2 * ks + g] + S(vy * vy) * min[5 * ks + g];
-        if constexpr (vx * vy != 0) p += S(vx * vy) * min[4 * ks + g];
+        S p = coef(px, py, 0);
+        if constexpr (vx != 0) p += S(-vx) * coef(px, py, 1) + S(vx * vx) * coef(px, py, 3);
+        if constexpr (vy != 0) p += S(-vy) * coef(px, py, 2) + S(vy * vy) * coef(px, py, 5);
+        if constexpr (vx * vy != 0) p += S(vx * vy) * coef(px, py, 4);
         f = wq * p;
         if constexpr (vx != 0) {
           constexpr int a = vx < 0 ? -vx : vx;
@@ -263,22 +284,6 @@ struct CoefTile {
 };
 
 namespace {
-
-// Two coefficients of a cell: (a0, bx), (by, cxx) or (cxy, cyy).
-template <typename S>
-using Pair = S __attribute__((ext_vector_type(2)));
-
-template <typename T>
-using lptr = __attribute__((address_space(3))) T*;
-
-// The same LDS address, opaque to the compiler: reads relative to it use
-// their small constant offsets directly instead of a new base register each.
-template <typename T>
-__device__ __forceinline__ lptr<const T> opaque(lptr<const T> p) {
-  uint32_t a = (uint32_t)(uintptr_t)p;
-  asm volatile("" : "+v"(a));
-  return (lptr<const T>)(uintptr_t)a;
-}
 
 // Raw buffer resource over `bytes` bytes at p (a wave-uniform address):
 // loads at offsets past the end return zero.  Word 3 = 0x00020000 sets the
@@ -448,7 +453,6 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S
   using T = CoefTile<L, RB>;
   constexpr int R = T::R, HW = T::HW;
   const int64_t n = t.n;
-  const gptr<const S> min = as_global(t.min);
   const int nx = d.nx, ny = d.ny;
   const int x0 = (tile % d.tiles_x) * kCoefTileW;
   const int y0 = (tile / d.tiles_x) * T::TH;
@@ -577,7 +581,7 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S
         S ladd = (S)(d.ladd_scale * U);
         // computed per cell in the band: keeps its products out of the common path
         asm volatile("" : "+v"(ladd));
-        m = add_links<L, S, DSW>(m, d, min, x, y, ladd, U, lat, cc);
+        m = add_links<L, S, DSW>(m, d, C, HW, x0 - R, y0 - R, x, y, ladd, U, lat, cc);
       }
     }
     const S drho = m.v[0], jx = m.v[1], jy = m.v[2];
