@@ -398,6 +398,16 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
   SolveState* st = d.state;
   const int64_t n = st->step;
   const bool coeffs = mode == 1 || (mode == 2 && d.mbuf[0] != nullptr);
+  // the epilogue's loads (drive entry, lock-in sums), issued before the
+  // force sums so that their latency overlaps them
+  const bool in_window = n >= d.lockin_first && n < d.lockin_first + d.lockin_count;
+  Drive dr{};
+  double lk[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (threadIdx.x == 0) {
+    dr = d.drive[n];
+    if (in_window)
+      for (int k = 0; k < 6; ++k) lk[k] = st->lockin[k];
+  }
   double fx = 0.0, fy = 0.0, fm = 0.0;
   if (coeffs) {
     const S* __restrict__ c = static_cast<const S*>(d.mbuf[n & 1]);
@@ -435,7 +445,6 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const Drive dr = d.drive[n];
     double sx = 0.0, sy = 0.0, sm = 0.0;
 #pragma unroll
     for (int k = 0; k < kBlock / 64; ++k) {
@@ -460,13 +469,13 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
     const int64_t h = n % d.hist_cap;
     d.hist[2 * h] = fx;
     d.hist[2 * h + 1] = fy;
-    if (n >= d.lockin_first && n < d.lockin_first + d.lockin_count) {
-      st->lockin[0] += fx * dr.s;
-      st->lockin[1] += fx * dr.c;
-      st->lockin[2] += fx;
-      st->lockin[3] += fy * dr.s;
-      st->lockin[4] += fy * dr.c;
-      st->lockin[5] += fy;
+    if (in_window) {
+      st->lockin[0] = lk[0] + fx * dr.s;
+      st->lockin[1] = lk[1] + fx * dr.c;
+      st->lockin[2] = lk[2] + fx;
+      st->lockin[3] = lk[3] + fy * dr.s;
+      st->lockin[4] = lk[4] + fy * dr.c;
+      st->lockin[5] = lk[5] + fy;
     }
     st->step = n + 1;
   }
