@@ -44,13 +44,14 @@ KERNELS = {
     2: ("lbm::coef_kernel<D2Q37, float, {rb}, false>", "coef.hip",
         "coef_kernel_beam_box_counters.json"),
 }
-# FP32 arithmetic per lattice update of the coefficient kernel's interior path
-# at 2 cells per thread (D2Q37), counted on the compiled code with FMA = 2 and
-# add or multiply = 1: 390 to form the 37 streamed populations from their
-# source cells' coefficients and gather their six moments (the per-source-cell
-# terms shared by the two cells of a lane, the per-row sums and the scatter),
-# 28 for the collision.
-COEF_FLOPS_PER_LU = 418
+# FP32 arithmetic per lattice update of the coefficient kernel (D2Q37) by
+# cells per thread K, counted on the compiled kernel without its wall-link
+# path (FMA = 2, add or multiply = 1, per lane over K): forming the 37
+# streamed populations from their source cells' coefficients and gathering
+# their six moments (source-cell terms shared by the K cells of a lane,
+# per-row sums and the scatter), plus 28 for the collision.
+COEF_FLOPS_PER_LU = {1: 469, 2: 423, 3: 401}
+COEF_K_DEFAULT = 3  # the library's tile when none is given
 # FP32 vector peak without packed FP32 (which this build does not use):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 78.6
@@ -321,19 +322,20 @@ def main():
     hbm = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
            "torch_copy": copy_gbs, "frac_of_torch_copy": hbm_gbs / copy_gbs,
            "algorithmic_bytes_per_launch": launch_bytes, "traffic": traffic}
-    kernel = KERNELS[repr_][0].format(rb=a.tile or 2)  # tile 0: 2 cells per thread
+    kernel = KERNELS[repr_][0].format(rb=a.tile or COEF_K_DEFAULT)
     if repr_ == 1:
         # populations: 296 B per update at ~1 kflop (3.4 flop/B) -> bound by HBM
         roofline = dict(hbm, bound="hbm")
     else:
-        # coefficients: 48 B and 418 flop per update (8.7 flop/B), just below
-        # the ridge of the FP32 vector units over HBM (78.6 / 8.0 = 9.8 flop/B),
-        # so the roofline bound is HBM; the vector-ALU figures go alongside
-        tflops = COEF_FLOPS_PER_LU * cells / avg_kernel_s / 1e12
+        # coefficients: 48 B and 401-469 flop per update (8.4-9.8 flop/B), at or
+        # below the ridge of the FP32 vector units over HBM (78.6 / 8.0 =
+        # 9.8 flop/B), so the roofline bound is HBM; the vector-ALU figures go
+        # alongside
+        flops = COEF_FLOPS_PER_LU[a.tile or COEF_K_DEFAULT]
+        tflops = flops * cells / avg_kernel_s / 1e12
         roofline = dict(hbm, bound="hbm")
         roofline["alu"] = {"achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": tflops / FP32_VALU_PEAK_TFLOPS,
-                           "flops_per_update": COEF_FLOPS_PER_LU}
+                           "frac": tflops / FP32_VALU_PEAK_TFLOPS, "flops_per_update": flops}
     roofline.update({"kernel": kernel, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches,
                      "kernel_timing": "start and stop events recorded by each launch itself "
                                       "(extended launch), a second pass of the same number of "

@@ -114,7 +114,7 @@ typedef struct lbm_params {
   uint32_t far;          /* LBM_FAR_* */
   uint32_t tile;         /* kernel tile.  Populations: 0 (= 1), 1, 2 or 4; one workgroup of
                             256*tile threads updates 256*tile consecutive cells, one per
-                            thread.  Coefficients: 0 (= 2), 1, 2 or 3 = K; one workgroup
+                            thread.  Coefficients: 0 (= 3), 1, 2 or 3 = K; one workgroup
                             of 256 threads updates a tile of 64 columns x 4K rows, K
                             cells per thread.  Batch members kept in the same
                             representation must agree. */

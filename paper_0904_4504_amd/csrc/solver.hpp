@@ -15,7 +15,7 @@ struct KernelEvents {
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
 constexpr int kCoefTileW = 64;   // coefficient kernel: tile width (one column per lane)
 constexpr int kCoefKMax = 3;     // coefficient kernel: tile variants K = 1..3
-constexpr int kCoefKDefault = 2;
+constexpr int kCoefKDefault = 3;
 
 // Rows of a coefficient-kernel tile of variant K: four wavefronts of K rows
 // each (K cells per thread).
