@@ -444,15 +444,15 @@ __device__ __forceinline__ void stage_load(const SolveDesc& d, const TileCtx<S>&
 // Moments, bounce-back corrections and collision of the RB cells of this
 // thread, from the staged tile in LDS (staged row r holds the pairs
 // (a0, bx), (by, cxx), (cxy, cyy) of its HW cells as three runs of HW): the
-// new coefficients of the cells in the lattice and the fluid go to res.
+// new coefficients of the cells in the lattice and the fluid go to res.  U:
+// the wall drive U_w of the step.
 template <class L, typename S, int RB, bool DSW>
 __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S>& t, int tile,
                                              const Pair<S>* C, const KernelLattice& lat,
                                              const CoefConst<S>& cc, int tid,
-                                             S (&res)[RB][6]) {
+                                             S (&res)[RB][6], double U) {
   using T = CoefTile<L, RB>;
   constexpr int R = T::R, HW = T::HW;
-  const int64_t n = t.n;
   const int nx = d.nx, ny = d.ny;
   const int x0 = (tile % d.tiles_x) * kCoefTileW;
   const int y0 = (tile / d.tiles_x) * T::TH;
@@ -577,7 +577,6 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S
     if (wave_has_wall) {
       const bool near = (y >= wy0 && y < wy1 && x >= wx0 && x < wx1) || (far_band && y >= ny - R);
       if (near) {
-        const double U = kread(&d.drive[n].u);
         S ladd = (S)(d.ladd_scale * U);
         // computed per cell in the band: keeps its products out of the common path
         asm volatile("" : "+v"(ladd));
@@ -674,6 +673,12 @@ __global__ __launch_bounds__(64 * kCoefWaves) void coef_kernel(const SolveDesc* 
   if (wi.tile < 0) return;
   const SolveDesc& d = descs[wi.solve];
   const TileCtx<S> ctx = tile_ctx<S>(d);
+  // wall drive of the step (for the links): a new table entry every step, so
+  // a cache miss; a vector load issued before the staging loads hides it
+  // behind them (a scalar load would share its counter with the LDS reads)
+  int nv = (int)ctx.n;
+  asm volatile("" : "+v"(nv));
+  const double U = as_global(d.drive)[nv].u;
   const int tid = (int)threadIdx.x;
   {
     // all loads of a thread are issued before the first LDS store, so the
@@ -684,7 +689,7 @@ __global__ __launch_bounds__(64 * kCoefWaves) void coef_kernel(const SolveDesc* 
   }
   __syncthreads();
   S res[RB][6];
-  compute_tile<L, S, RB, DSW>(d, ctx, wi.tile, C, lat, cc, tid, res);
+  compute_tile<L, S, RB, DSW>(d, ctx, wi.tile, C, lat, cc, tid, res, U);
   store_tile<L, S, RB>(d, ctx, wi.tile, tid, res);
 }
 
