@@ -187,7 +187,8 @@ __device__ __forceinline__ S pull_edge_bb(const EdgeGeom& g, const S* __restrict
     }
   }
   term = moving ? (S)(wq * vx * ladd) : S(-0.0);
-  const S* src = zero ? reinterpret_cast<const S*>(&kZeroWord) : fin + (pl * g.qs + py * g.ys + px);
+  const S* src =
+      zero ? reinterpret_cast<const S*>(&kZeroWord) : fin + (pl * g.qs + py * g.ys + px);
   return *src;
 }
 
