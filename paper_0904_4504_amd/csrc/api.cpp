@@ -62,11 +62,14 @@ std::vector<char> coef_wall_tiles(const lbm_params* p, const Layout& lay, int R)
 }
 
 void order_coef_tiles(std::vector<WorkItem>* front, std::vector<WorkItem>* rest, int32_t solve,
-                      const std::vector<char>& wall, int32_t ntiles, int32_t span) {
+                      const std::vector<char>& wall, int32_t ntiles, int32_t span, bool banded) {
   for (int32_t t = 0; t < ntiles; ++t)
     if (wall[t]) front->push_back(WorkItem{solve, t});
   const size_t from = rest->size();
-  order_tiles(rest, solve, ntiles, span);
+  if (banded)
+    order_tiles_banded(rest, solve, ntiles, span);
+  else
+    order_tiles(rest, solve, ntiles, span);
   for (size_t i = from; i < rest->size(); ++i) {
     WorkItem& w = (*rest)[i];
     if (w.tile >= 0 && wall[w.tile]) w.tile = -1;
@@ -78,7 +81,21 @@ void join_front(std::vector<WorkItem>* front, const std::vector<WorkItem>& rest)
   front->insert(front->end(), rest.begin(), rest.end());
 }
 
-// Work-list length order_tiles produces for one solve starting aligned.
+void order_tiles_banded(std::vector<WorkItem>* out, int32_t solve, int32_t ntiles,
+                        int32_t span) {
+  while (out->size() % 8) out->push_back(WorkItem{solve, -1});
+  span = std::max<int32_t>(1, span);
+  const int32_t nrows = (ntiles + span - 1) / span;
+  const int32_t band = (nrows + 7) / 8, per = band * span;
+  for (int32_t j = 0; j < per; ++j)
+    for (int32_t x = 0; x < 8; ++x) {
+      const int32_t row = x * band + j / span, t = row * span + j % span;
+      out->push_back(WorkItem{solve, row < nrows && t < ntiles ? t : -1});
+    }
+}
+
+// Work-list length order_tiles (and order_tiles_banded) produces for one
+// solve starting aligned.
 int64_t ordered_length(int64_t ntiles, int64_t span) {
   span = std::max<int64_t>(1, span);
   const int64_t nrows = (ntiles + span - 1) / span;
@@ -453,7 +470,7 @@ int init_solver(lbm_solver* s) {
   if (lay.mom) {
     std::vector<WorkItem> rest;
     order_coef_tiles(&mwork, &rest, 0, coef_wall_tiles(p, lay, s->lat.R), lay.mntiles,
-                     lay.tiles_x);
+                     lay.tiles_x, 2 * lay.mbuf_bytes <= kBandedStateBytes);
     join_front(&mwork, rest);
     if ((int32_t)mwork.size() != lay.mnwork) return LBM_EINVAL;
   }

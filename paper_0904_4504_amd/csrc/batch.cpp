@@ -82,6 +82,11 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
   // tiles of the launch), then the rest
   std::vector<WorkItem> group[4], front[4], work;
   std::vector<int32_t> solves;
+  uint64_t state[4] = {0, 0, 0, 0};  // coefficient state bytes per group
+  for (size_t i = 0; i < act.size(); ++i) {
+    const Layout& lay = act[i]->lay;
+    if (lay.mom) state[2 + (act[i]->p.wall != LBM_WALL_BB)] += 2 * lay.mbuf_bytes;
+  }
   for (size_t i = 0; i < act.size(); ++i) {
     descs.push_back(act[i]->desc);
     solves.push_back((int32_t)i);
@@ -89,7 +94,8 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
     const int k = (lay.mom ? 2 : 0) + (act[i]->p.wall != LBM_WALL_BB);
     if (lay.mom) {
       order_coef_tiles(&front[k], &group[k], (int32_t)i,
-                       coef_wall_tiles(&act[i]->p, lay, act[i]->lat.R), lay.mntiles, lay.tiles_x);
+                       coef_wall_tiles(&act[i]->p, lay, act[i]->lat.R), lay.mntiles, lay.tiles_x,
+                       state[k] <= kBandedStateBytes);
     } else {
       order_tiles(&group[k], (int32_t)i, lay.ntiles,
                   (act[i]->p.nx + lay.cells_per_tile - 1) / lay.cells_per_tile);

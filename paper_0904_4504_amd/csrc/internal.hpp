@@ -57,13 +57,25 @@ struct Layout {
 // Append the tiles of one solve to a launch work list in XCD-aware order
 // (rows of `span` tiles dealt to the 8 XCDs in turn).
 void order_tiles(std::vector<WorkItem>* out, int32_t solve, int32_t ntiles, int32_t span);
+// The same tiles with each XCD taking one contiguous band of tile rows (the
+// halo rows shared by vertically adjacent tiles stay in that XCD's L2);
+// the same length as order_tiles.
+void order_tiles_banded(std::vector<WorkItem>* out, int32_t solve, int32_t ntiles,
+                        int32_t span);
 // Coefficient-kernel tiles of a solve with a wall link (mask over its tiles).
 std::vector<char> coef_wall_tiles(const lbm_params* p, const Layout& lay, int R);
 // The tiles of one coefficient solve: its wall tiles to `front` (they are the
 // slowest of a launch, so they start first), the rest to `rest` in the order
-// of order_tiles with the wall tiles made no-ops (keeping its XCD structure).
+// of order_tiles_banded (banded) or order_tiles with the wall tiles made
+// no-ops (keeping the XCD structure).
 void order_coef_tiles(std::vector<WorkItem>* front, std::vector<WorkItem>* rest, int32_t solve,
-                      const std::vector<char>& wall, int32_t ntiles, int32_t span);
+                      const std::vector<char>& wall, int32_t ntiles, int32_t span, bool banded);
+// Coefficient launches whose two state buffers together take at most this
+// many bytes stay in the 256 MB last-level cache between steps; their tiles
+// go in bands (reuse of the halo rows within an XCD's L2), larger ones in the
+// row-interleaved order (adjacent rows in flight on all XCDs at once, the
+// better pattern when the state streams from HBM).
+constexpr uint64_t kBandedStateBytes = (uint64_t)192 << 20;
 // front, padded with no-ops to a multiple of 8 items, then rest.
 void join_front(std::vector<WorkItem>* front, const std::vector<WorkItem>& rest);
 
