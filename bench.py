@@ -55,9 +55,18 @@ COEF_K_DEFAULT = 3  # the library's tile when none is given
 # FP32 vector peak without packed FP32 (which this build does not use):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 78.6
-def kernel_hash(src):
-    with open(os.path.join(CSRC, src), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+# host sources that shape what a kernel's counters measure besides its own
+# file: the work order, tile sizes and layout
+ORDER_SOURCES = ("api.cpp", "batch.cpp", "internal.hpp", "solver.hpp")
+
+
+def sources_hash(src):
+    """sha256 (16 hex) over the kernel's source file and ORDER_SOURCES."""
+    h = hashlib.sha256()
+    for name in (src,) + ORDER_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def workload(name, steps, warmup):
@@ -106,14 +115,14 @@ def copy_ceiling(stream, nbytes=1 << 31, reps=5):
 
 def traffic_from_profile(repr_):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source; else None."""
+    taken on the current kernel and host sources; else None."""
     _, src, counters = KERNELS[repr_]
     try:
         with open(os.path.join(ROOT, "profiles", counters)) as fh:
             prof = json.load(fh)
     except (OSError, ValueError):
         return None
-    if prof.get("kernel_source_sha256_16") != kernel_hash(src):
+    if prof.get("sources_sha256_16") != sources_hash(src):
         return None
     return prof.get("hbm_bytes_per_launch")
 
