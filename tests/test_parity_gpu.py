@@ -493,6 +493,43 @@ def test_batch_alone_equals_mix_with_diffuse_walls(P):
         sv.close()
 
 
+def test_large_batch_matches_alone(P):
+    """Five perturbed 1024 x 1024 boxes: as one batch their coefficient state
+    (about 250 MB) is past the size up to which the tiles go in bands per XCD,
+    so the batch runs the row-interleaved work order while each solve alone
+    runs the banded one; forces and final states are bit-identical."""
+    import torch
+    stream = torch.cuda.Stream()
+    solves = [W.beam_box(tw).scaled(12, 8) for tw in (0.1, 0.3, 1.0, 3.0, 10.0)]
+    v, w, th = P.lattice(37)
+    f0 = _f0(solves[0], w, seed=11, amp=1e-3)
+    ref = []
+    for s in solves:
+        with P.Solver(P.params_from_solve(s), stream=stream) as sv:
+            sv.set_populations(f0)
+            sv.step(1)            # the first step after a load runs alone
+            sv.step(s.nsteps - 1)
+            fx, fy = sv.force_history(0, s.nsteps)
+            ref.append((fx, fy, sv.get_deviations()))
+    svs = [P.Solver(P.params_from_solve(s), stream=stream) for s in solves]
+    b = P.Batch(stream)
+    try:
+        for sv in svs:
+            sv.set_populations(f0)
+            sv.step(1)
+            b.add(sv)
+        b.step(solves[0].nsteps - 1)
+        b.synchronize()
+        for s, sv, (rx, ry, rd) in zip(solves, svs, ref):
+            fx, fy = sv.force_history(0, s.nsteps)
+            assert np.array_equal(fx, rx) and np.array_equal(fy, ry), s.name
+            assert np.array_equal(sv.get_deviations(), rd), s.name
+    finally:
+        b.close()
+        for sv in svs:
+            sv.close()
+
+
 def test_graph_replays_match_eager(P):
     """Replays of the captured graph, with eager work and synchronisation
     between them, each agree with plain launches."""
