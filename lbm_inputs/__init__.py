@@ -182,6 +182,33 @@ def serving_trace(rate, count, seed=5, period=1024, transient_periods=10, window
     return out
 
 
+def batch_parity_subsample(seed=40, count=256):
+    """Indices into batch_sweep(count) of the seeded parity subsample: the
+    solve with the fewest fluid cells, the one with the most, and two more
+    drawn without replacement from the rest by PCG64(seed).  Returns
+    (smallest, largest, [two drawn], sorted)."""
+    solves = batch_sweep(count)
+    cells = np.array([s.fluid_cells for s in solves])
+    small, large = int(np.argmin(cells)), int(np.argmax(cells))
+    rest = [i for i in range(count) if i not in (small, large)]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    drawn = sorted(int(i) for i in rng.choice(rest, 2, replace=False))
+    return small, large, drawn
+
+
+def wide_plate(tau_omega, far, nx=64, ny=2048, period=1024, transient_periods=10,
+               window_periods=10, storage="f32dev"):
+    """D2Q37 plate wide enough (nx >= 64) to be kept as H2 coefficients, with
+    the stationary far wall (far=FAR_WALL) or the rest-equilibrium far field
+    (far=FAR_EQ): the plates of the batch sweep run this way."""
+    omega = 2 * math.pi / period
+    steps = (transient_periods + window_periods) * period
+    return Solve(Q=37, geometry=PLATE, far=far, nx=nx, ny=ny, tau=tau_lb(tau_omega, omega),
+                 omega=omega, nsteps=steps, window_first=transient_periods * period,
+                 window_count=window_periods * period, storage=storage, tau_omega=tau_omega,
+                 name=f"wide_plate_{far}_tw{tau_omega:g}")
+
+
 # --------------------------------------------------------------- noise
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)

@@ -178,7 +178,11 @@ class Solver:
         sp = C.c_void_p(self.stream.cuda_stream)
         if memory == "torch":
             nbytes = required_bytes(params)
-            self._mem = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            # allocated on the solver's stream: the caching allocator orders
+            # reuse of a freed block only on the stream it was allocated on,
+            # and the library initialises and steps this memory on self.stream
+            with torch.cuda.stream(self.stream):
+                self._mem = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
             ptr = self._mem.data_ptr()
             ptr += (-ptr) % 256
             _check(lib().lbm_create_in(C.byref(params), sp, C.c_void_p(ptr), nbytes,

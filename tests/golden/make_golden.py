@@ -8,7 +8,13 @@ steps plus the last 64 steps in full.
   python tests/golden/make_golden.py stokes_plate          # D2Q9 4x256, 160 850 steps
   python tests/golden/make_golden.py plate_sweep           # D2Q37 4x2048, 5 tau*omega
   python tests/golden/make_golden.py beam_box [tw ...]     # D2Q37 1024^2 box, hours
+  python tests/golden/make_golden.py batch_subsample       # seeded 4 of the 256-solve batch
+  python tests/golden/make_golden.py wide_plate            # 64x2048 plates, tau*omega 0.01, 100
   options: --threads N
+
+The batch subsample runs each drawn solve for its full 20 480 steps, except
+the largest (2026 x 2026 cells), which runs 4 periods (4096 steps, lock-in
+over the last 2): at the oracle's few MLUPS a full run takes hours.
 """
 import argparse
 import dataclasses
@@ -24,6 +30,10 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import lbm_inputs as W  # noqa: E402
 import oracle as O  # noqa: E402
+
+
+# run length of the largest solve of the batch subsample (4 periods)
+LARGEST_STEPS = 4096
 
 
 def oracle_params(s, threads):
@@ -71,7 +81,8 @@ def write(name, obj):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("case", choices=["stokes_plate", "plate_sweep", "beam_box"])
+    ap.add_argument("case", choices=["stokes_plate", "plate_sweep", "beam_box", "batch_subsample",
+                                     "wide_plate"])
     ap.add_argument("tau_omega", nargs="*", type=float)
     ap.add_argument("--threads", type=int, default=0)
     a = ap.parse_args()
@@ -83,6 +94,21 @@ def main():
         for tw in a.tau_omega or W.PLATE_SWEEP_TAU_OMEGA:
             s = W.plate_sweep(tw, storage="f64")
             write(f"plate_sweep_tw{tw:g}", run_case(s, "f64", a.threads, 97))
+    elif a.case == "batch_subsample":
+        small, large, drawn = W.batch_parity_subsample()
+        solves = W.batch_sweep()
+        for i in [small] + drawn + [large]:
+            s = dataclasses.replace(solves[i], storage="f64")
+            if i == large:
+                s = s.scaled(LARGEST_STEPS, LARGEST_STEPS // 2)
+            out = run_case(s, "f64", a.threads, 97)
+            out["batch_index"] = i
+            write(f"batch_{i}", out)
+    elif a.case == "wide_plate":
+        for far in (W.FAR_WALL, W.FAR_EQ):
+            for tw in a.tau_omega or (0.01, 100.0):
+                s = W.wide_plate(tw, far, storage="f64")
+                write(s.name, run_case(s, "f64", a.threads, 97))
     else:
         for tw in a.tau_omega or W.BEAM_TAU_OMEGA:
             s = W.beam_box(tw, storage="f64")
