@@ -55,7 +55,9 @@ enum {
   LBM_EHIP = -3,      /* a HIP runtime call failed (no device, launch failure, ...) */
   LBM_ERANGE = -4,    /* step beyond max_steps, or history request outside the ring */
   LBM_EUNSTABLE = -5, /* a cell reached rho <= 0 or a non-finite value */
-  LBM_EABI = -6       /* params.abi_version != LBM_ABI_VERSION */
+  LBM_EABI = -6,      /* params.abi_version != LBM_ABI_VERSION */
+  LBM_ESCRATCH = -7   /* lbm_create_static: the parameters need more than
+                         LBM_STATIC_SCRATCH_BYTES, or a live solver holds the array */
 };
 
 enum { LBM_D2Q9 = 9, LBM_D2Q37 = 37 };
@@ -162,6 +164,25 @@ int lbm_create(const lbm_params* p, void* hip_stream, lbm_solver** out);
  * caller keeps it alive until lbm_destroy. */
 int lbm_create_in(const lbm_params* p, void* hip_stream, void* dev_buf, uint64_t bytes,
                   lbm_solver** out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * lbm_create_in, but the solver's device memory is the library's own static
+ * scratch array of LBM_STATIC_SCRATCH_BYTES on the current device (one array
+ * per device, held until the process ends).  No device memory is allocated
+ * or freed by this call, by lbm_step on the solver or by its lbm_destroy;
+ * host-side bookkeeping uses the C++ heap.  The solver steps without HIP
+ * graphs (instantiating one may allocate).  Everything the solver reads is
+ * initialised by this call (rest state, counters, tables), so whatever an
+ * earlier solver left in the array does not matter.  One such solver per
+ * device at a time: while it lives (until lbm_destroy), another
+ * lbm_create_static on that device returns LBM_ESCRATCH, as do parameters
+ * whose lbm_required_bytes exceeds LBM_STATIC_SCRATCH_BYTES.  Launches of two
+ * processes' static solvers on one device do not share the array (each
+ * process has its own copy); work enqueued on the array by a destroyed solver
+ * has completed (lbm_destroy waits). */
+#define LBM_STATIC_SCRATCH_BYTES ((uint64_t)64 << 20)
+int lbm_create_static(const lbm_params* p, void* hip_stream, lbm_solver** out);
 
 /* Enqueue nsteps steps on the solver's stream and return without waiting.
  * Calls of 32 steps or more replay a HIP graph of 32 steps that the first

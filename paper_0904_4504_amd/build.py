@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["lattice.cpp", "api.cpp", "batch.cpp", "kernels.hip", "coef.hip"]
+SOURCES = ["lattice.cpp", "api.cpp", "batch.cpp", "kernels.hip", "coef.hip", "static_solver.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code.

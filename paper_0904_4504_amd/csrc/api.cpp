@@ -526,8 +526,10 @@ int init_solver(lbm_solver* s) {
   return hip_rc(hipStreamSynchronize(st));
 }
 
-int create_common(const lbm_params* p, void* stream, void* dev_buf, uint64_t bytes,
-                  lbm_solver** out) {
+}  // namespace
+
+int lbm::create_solver(const lbm_params* p, void* stream, void* dev_buf, uint64_t bytes,
+                       bool graphs, lbm_solver** out) {
   if (!out) return LBM_EINVAL;
   *out = nullptr;
   lbm_solver* s = new (std::nothrow) lbm_solver();
@@ -560,6 +562,7 @@ int create_common(const lbm_params* p, void* stream, void* dev_buf, uint64_t byt
     s->base = static_cast<char*>(ptr);
     s->owned = true;
   }
+  s->graphs_ok = graphs;
   rc = init_solver(s);
   if (rc) {
     if (s->owned) (void)hipFree(s->base);
@@ -569,8 +572,6 @@ int create_common(const lbm_params* p, void* stream, void* dev_buf, uint64_t byt
   *out = s;
   return LBM_OK;
 }
-
-}  // namespace
 
 // One step of a single solver: the population kernel, the population kernel
 // writing coefficients (first step after populations were loaded into a
@@ -696,13 +697,13 @@ int lbm_required_bytes(const lbm_params* p, uint64_t* bytes) {
 }
 
 int lbm_create(const lbm_params* p, void* hip_stream, lbm_solver** out) {
-  return create_common(p, hip_stream, nullptr, 0, out);
+  return create_solver(p, hip_stream, nullptr, 0, true, out);
 }
 
 int lbm_create_in(const lbm_params* p, void* hip_stream, void* dev_buf, uint64_t bytes,
                   lbm_solver** out) {
   if (!dev_buf) return LBM_EINVAL;
-  return create_common(p, hip_stream, dev_buf, bytes, out);
+  return create_solver(p, hip_stream, dev_buf, bytes, true, out);
 }
 
 int lbm_step(lbm_solver* s, int64_t nsteps) {
@@ -990,6 +991,7 @@ int lbm_destroy(lbm_solver* s) {
   int rc = hipStreamSynchronize(s->stream) == hipSuccess ? LBM_OK : LBM_EHIP;
   if (s->graph) (void)hipGraphExecDestroy(s->graph);
   if (s->owned && hipFree(s->base) != hipSuccess) rc = LBM_EHIP;
+  if (s->in_scratch) release_scratch(s->device);
   delete s;
   return rc;
 }
@@ -1003,6 +1005,8 @@ const char* lbm_strerror(int code) {
     case LBM_ERANGE: return "out of range";
     case LBM_EUNSTABLE: return "unstable: non-positive or non-finite density";
     case LBM_EABI: return "ABI version mismatch";
+    case LBM_ESCRATCH:
+      return "static scratch buffer too small for these parameters, or in use by a live solver";
     default: return "unknown error";
   }
 }

@@ -112,5 +112,19 @@ struct lbm_solver {
   // step index from the device, so one graph serves every later chunk)
   hipGraphExec_t graph = nullptr;
   bool graphs_ok = true;
+  // device memory is the library's static scratch array of `device`
+  // (lbm_create_static), released by lbm_destroy
+  bool in_scratch = false;
 };
+
+namespace lbm {
+// Create a solver in caller-owned device memory (dev_buf, bytes) or, with
+// dev_buf null, in memory the library allocates.  graphs: lbm_step may
+// capture and replay HIP graphs (off: every step launches directly).
+int create_solver(const lbm_params* p, void* stream, void* dev_buf, uint64_t bytes, bool graphs,
+                  lbm_solver** out);
+// Mark the static scratch array of `device` free again (lbm_destroy of a
+// solver created by lbm_create_static).
+void release_scratch(int device);
+}  // namespace lbm
 

@@ -13,7 +13,9 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm.so")
 
 ABI_VERSION = 2
-OK, EINVAL, ENOMEM, EHIP, ERANGE, EUNSTABLE, EABI = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EHIP, ERANGE, EUNSTABLE, EABI, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+# size of the library's static scratch array (lbm_create_static), per device
+STATIC_SCRATCH_BYTES = 64 << 20
 D2Q9, D2Q37 = 9, 37
 STORE_F64, STORE_F32_DEV = 0, 1
 COLL_REGULARIZED, COLL_BGK = 0, 1
@@ -30,7 +32,7 @@ EXPORTS = (
     "lbm_strerror", "lbm_seek", "lbm_get_deviations", "lbm_set_deviations", "lbm_batch_create", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_size", "lbm_batch_step", "lbm_batch_synchronize", "lbm_batch_set_graphs",
     "lbm_batch_timing", "lbm_batch_kernel_time", "lbm_batch_destroy", "lbm_state_size",
-    "lbm_get_state", "lbm_set_state", "lbm_representation",
+    "lbm_get_state", "lbm_set_state", "lbm_representation", "lbm_create_static",
 )
 
 
@@ -73,6 +75,7 @@ def lib():
         L.lbm_required_bytes.argtypes = [P, C.POINTER(C.c_uint64)]
         L.lbm_create.argtypes = [P, vp, C.POINTER(vp)]
         L.lbm_create_in.argtypes = [P, vp, vp, C.c_uint64, C.POINTER(vp)]
+        L.lbm_create_static.argtypes = [P, vp, C.POINTER(vp)]
         L.lbm_step.argtypes = [vp, C.c_int64]
         L.lbm_synchronize.argtypes = [vp]
         L.lbm_steps_done.argtypes = [vp, C.POINTER(C.c_int64)]
@@ -162,8 +165,10 @@ class Solver:
     """One solve on the current GPU.
 
     memory="torch": device memory is a torch uint8 tensor handed to
-    lbm_create_in; memory="library": lbm_create allocates it.  The stream is
-    torch's current stream unless one is given (a torch.cuda.Stream)."""
+    lbm_create_in; memory="library": lbm_create allocates it;
+    memory="static": the library's static scratch array (lbm_create_static,
+    no device allocation; one such solver per device at a time).  The stream
+    is torch's current stream unless one is given (a torch.cuda.Stream)."""
 
     def __init__(self, params, stream=None, memory="torch"):
         import torch
@@ -187,6 +192,9 @@ class Solver:
             ptr += (-ptr) % 256
             _check(lib().lbm_create_in(C.byref(params), sp, C.c_void_p(ptr), nbytes,
                                        C.byref(self._h)), "lbm_create_in")
+        elif memory == "static":
+            _check(lib().lbm_create_static(C.byref(params), sp, C.byref(self._h)),
+                   "lbm_create_static")
         else:
             _check(lib().lbm_create(C.byref(params), sp, C.byref(self._h)), "lbm_create")
 
