@@ -1,24 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the lattice-BGK hot path on one MI355X.
 
-Default workload (beam_box): the 1024 x 1024 domain with a 32 x 16 body
-oscillating along x, D2Q37, FP32 deviation storage with FP64 force and
-lock-in, at tau*omega = 0.1, 1 and 10.  The three solves run as one batch,
-their state kept as the six H2 coefficients per cell: one step = one
-stream-collide launch over the tiles of all three lattices (pull advection of
-the 37 populations from the coefficients, bounce-back with the moving-wall
-term, moments, H2 equilibrium, regularized collision) plus one launch that
-computes each solve's FP64 momentum-exchange force, appends it to the history
-and accumulates the lock-in sums.  Inputs are resident in HBM before timing.
+Default workload (batch): the 256 uneven solves of the batched sweep (sides
+256-2048 cells, aspect 1:1, 2:1, 4:1, a plate or a rectangle of 8-64 cells
+per side, tau*omega log-uniform in [1e-2, 1e2], U0 = 1e-3, D2Q37, FP32
+deviation storage with FP64 force and lock-in), drawn from one seeded PCG64
+stream, advanced together as one batch with the tile the autotuner picks.
+Every member keeps its state as the six H2 coefficients per cell (48 B per
+update in FP32): 13 GB of state, 50 times the 256 MB last-level cache, so
+every step streams it from HBM.  One step = one stream-collide launch over
+the tiles of all 256 lattices (pull advection of the 37 populations from the
+coefficients, bounce-back with the moving-wall term, moments, H2
+equilibrium, regularized collision) plus one launch that computes each
+solve's FP64 momentum-exchange force, appends it to the history and
+accumulates the lock-in sums.  The state is created and warmed up on the
+device before the timed steps.
+
+Other workloads: beam_box (3 x 1024^2 with the 32 x 16 body; its 151 MB of
+coefficient state stays in the last-level cache between steps, so its
+bandwidth is not an HBM figure), plate_sweep (5 plates of 4 x 2048).
 
 Prints one JSON line: MLUPS (fluid-cell updates per second); the dominant
-kernel against its roofline (HIP events around every launch of that kernel in
-the timed region): the population kernel against the 8 TB/s HBM peak, the
-coefficient kernel (48 B per update) against the FP32 vector peak, with its
-algorithmic HBM bandwidth beside it; and the CPU oracle timed on a bounded
-sample on this host.
+kernel against its roofline (each launch of it records its own start and stop
+events over a second pass of K steps); and the CPU oracle timed on a bounded
+sample of the workload on this host, on all its cores and on one.
 
-    python bench.py [--steps K] [--warmup W] [--workload beam_box|plate_sweep]
+    python bench.py [--steps K] [--warmup W] [--workload batch|beam_box|plate_sweep]
     python bench.py --workload batch_sweep   # sweep solves/s, batched vs plain loop
     python bench.py --workload serving       # p50/p99 latency, batched vs plain loop
 """
@@ -37,12 +44,16 @@ sys.path.insert(0, ROOT)
 METRIC = ("MLUPS & HBM GB/s (%peak); sweep solves/s + p50/p99 latency vs plain loop")
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_0904_4504_amd", "csrc")
-# dominant kernel per device representation: (name, source file, counters file)
+# dominant kernel per device representation: (name, source file)
 KERNELS = {
-    1: ("lbm::step_kernel<D2Q37, float, false, false, 256, false>", "kernels.hip",
-        "step_kernel_beam_box_counters.json"),
-    2: ("lbm::coef_kernel<D2Q37, float, {rb}, false>", "coef.hip",
-        "coef_kernel_beam_box_counters.json"),
+    1: ("lbm::step_kernel<D2Q37, float, false, false, 256, false>", "kernels.hip"),
+    2: ("lbm::coef_kernel<D2Q37, float, {rb}, false>", "coef.hip"),
+}
+# committed rocprofv3 counters per (representation, workload)
+COUNTERS = {
+    (1, "beam_box"): "step_kernel_beam_box_counters.json",
+    (2, "beam_box"): "coef_kernel_beam_box_counters.json",
+    (2, "batch"): "coef_kernel_batch_counters.json",
 }
 # FP32 arithmetic per lattice update of the coefficient kernel (D2Q37) by
 # cells per thread K, counted on the compiled kernel without its wall-link
@@ -72,7 +83,12 @@ def sources_hash(src):
 def workload(name, steps, warmup):
     import lbm_inputs as W
     n = warmup + steps
-    if name == "beam_box":
+    if name == "batch":
+        solves = W.batch_sweep()
+        desc = ("batch: the 256 seeded solves of the batched sweep (sides 256-2048, aspect "
+                "1/2/4, plate or 8-64-cell rectangle, tau*omega 1e-2..1e2, U0 1e-3), D2Q37 "
+                "FP32-deviation storage, FP64 force + lock-in, one batch, autotuned tile")
+    elif name == "beam_box":
         solves = [W.beam_box(tw) for tw in W.BEAM_TAU_OMEGA]
         desc = ("beam_box: 1024x1024 domain, 32x16 body centred, rest-equilibrium far field, "
                 "D2Q37 FP32-deviation storage, FP64 force + lock-in, tau*omega {0.1, 1, 10} "
@@ -113,10 +129,14 @@ def copy_ceiling(stream, nbytes=1 << 31, reps=5):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-def traffic_from_profile(repr_):
-    """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel and host sources; else None."""
-    _, src, counters = KERNELS[repr_]
+def traffic_from_profile(repr_, name):
+    """HBM bytes per launch from committed rocprofv3 counters of this kernel
+    and workload, if they were taken on the current kernel and host sources;
+    else None."""
+    _, src = KERNELS[repr_]
+    counters = COUNTERS.get((repr_, name))
+    if counters is None:
+        return None
     try:
         with open(os.path.join(ROOT, "profiles", counters)) as fh:
             prof = json.load(fh)
@@ -127,29 +147,39 @@ def traffic_from_profile(repr_):
     return prof.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(solve, budget_s):
-    """The FP64 oracle on this host's cores on a bounded sample of the workload."""
+def _oracle_rate(solve, threads, budget_s):
+    """(MLUPS, steps, seconds) of the FP64 oracle on `threads` threads over
+    about budget_s seconds of steps of `solve` from rest."""
     import oracle as O
     import lbm_inputs as W
-    cores = len(os.sched_getaffinity(0))
     p = O.OracleParams(
         Q=solve.Q, nx=solve.nx, ny=solve.ny, tau=solve.tau, omega=solve.omega, u0=solve.u0,
         geometry=O.GEOM_BOX if solve.geometry == W.BOX else O.GEOM_PLATE,
         far=O.FAR_EQ if solve.far == W.FAR_EQ else O.FAR_WALL,
         box_x0=solve.box[0], box_y0=solve.box[1], box_lx=solve.box[2], box_ly=solve.box[3],
-        nthreads=cores)
-    O.run(p, 2)  # first call: page in, thread pool
+        nthreads=threads)
+    O.run(p, 1)  # first call: page in, thread pool
     t0 = time.perf_counter()
-    O.run(p, 8)
-    per_step = (time.perf_counter() - t0) / 8
-    nsteps = max(8, min(4000, int(budget_s / max(per_step, 1e-6))))
+    O.run(p, 2)
+    per_step = (time.perf_counter() - t0) / 2
+    nsteps = max(2, min(4000, int(budget_s / max(per_step, 1e-6))))
     t0 = time.perf_counter()
     O.run(p, nsteps)
     dt = time.perf_counter() - t0
-    mlups = solve.fluid_cells * nsteps / dt / 1e6
+    return solve.fluid_cells * nsteps / dt / 1e6, nsteps, dt
+
+
+def cpu_baseline(solve, budget_s):
+    """The FP64 oracle on a bounded sample of the workload (one of its solves
+    from rest), on all of this host's cores and on one core."""
+    cores = len(os.sched_getaffinity(0))
+    mlups, n, dt = _oracle_rate(solve, cores, budget_s)
+    mlups1, n1, dt1 = _oracle_rate(solve, 1, budget_s / 3)
     return {"value": mlups, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{solve.name}: {nsteps} steps of one {solve.nx}x{solve.ny} lattice from "
-                      f"rest, FP64 oracle, OpenMP over rows on {cores} threads, {dt:.1f} s"}
+            "value_1core": mlups1,
+            "sample": f"{solve.name}: one {solve.nx}x{solve.ny} lattice of the workload from "
+                      f"rest, FP64 oracle, OpenMP over rows: {n} steps on {cores} threads in "
+                      f"{dt:.1f} s; {n1} steps on 1 thread in {dt1:.1f} s"}
 
 
 def sweep_mode(a):
@@ -254,11 +284,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="beam_box")
-    ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--workload", default="batch")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--representation", type=int, default=0,
-                    help="0 automatic, 1 populations, 2 H2 coefficients")
+                    help="0 automatic, 1 populations, 2 (3: without loads) H2 coefficients")
     ap.add_argument("--tile", type=int, default=0,
                     help="kernel tile (cells per thread of the population or the coefficient "
                          "kernel); 0 = library default")
@@ -284,11 +314,20 @@ def main():
         return serving_mode(a)
     solves, desc = workload(a.workload, a.steps, a.warmup)
     stream = torch.cuda.Stream()
+    tile, tile_ms = a.tile, None
     with torch.cuda.stream(stream):
+        if a.workload == "batch" and not a.tile and a.representation == 0:
+            # the batched sweep runs with the tile the autotuner picks
+            from paper_0904_4504_amd import autotune
+            tile, tile_ms = autotune.tune(solves, stream=stream)
+        # the runs start from rest: coefficient members need no population buffer
         solvers = [P.Solver(P.params_from_solve(s, representation=a.representation,
-                                                tile=a.tile),
+                                                tile=tile, loads=False),
                             stream=stream) for s in solves]
-        repr_ = solvers[0].representation
+        reprs = {sv.representation for sv in solvers}
+        if len(reprs) != 1:
+            raise SystemExit(f"members in several representations {reprs}")
+        repr_ = reprs.pop()
         batch = P.Batch(stream)
         for sv in solvers:
             batch.add(sv)
@@ -312,37 +351,42 @@ def main():
         batch.synchronize()
         kern_ms, launches = batch.kernel_time()
         batch.timing(False)
-        z = [sv.impedance() for sv in solvers]
+        state_bytes = sum(P.required_bytes(sv.p) for sv in solvers)
         batch.close()
         for sv in solvers:
             sv.close()
+        del solvers
+        torch.cuda.empty_cache()
 
     cells = sum(s.fluid_cells for s in solves)
     Q = solves[0].Q
-    # algorithmic bytes per lattice update: read and write the stored state once
-    # (Q populations, or the six H2 coefficients of the regularized state)
+    # algorithmic bytes per lattice update: read and write the stored state
+    # once -- the Q populations, or the six H2 coefficients that hold the
+    # regularized state exactly
     bytes_per_lu = 2 * (Q if repr_ == 1 else 6) * 4
     mlups = cells * a.steps / (elapsed_ms / 1e3) / 1e6
     avg_kernel_s = kern_ms / 1e3 / launches
     launch_bytes = bytes_per_lu * cells
     hbm_gbs = launch_bytes / avg_kernel_s / 1e9
-    traffic = traffic_from_profile(repr_)
+    traffic = traffic_from_profile(repr_, a.workload)
     copy_gbs = copy_ceiling(stream)
+    # the state read and written by one step: 2 buffers of the device state
+    # (coefficients or populations) of every member; above the 256 MB
+    # last-level cache it streams from HBM every step
+    resident = "hbm" if state_bytes > (256 << 20) else "last-level cache (256 MB)"
     hbm = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
            "torch_copy": copy_gbs, "frac_of_torch_copy": hbm_gbs / copy_gbs,
-           "algorithmic_bytes_per_launch": launch_bytes, "traffic": traffic}
-    kernel = KERNELS[repr_][0].format(rb=a.tile or COEF_K_DEFAULT)
-    if repr_ == 1:
-        # populations: 296 B per update at ~1 kflop (3.4 flop/B) -> bound by HBM
-        roofline = dict(hbm, bound="hbm")
-    else:
+           "algorithmic_bytes_per_launch": launch_bytes, "traffic": traffic,
+           "device_bytes": state_bytes, "state_streams_from": resident}
+    kernel = KERNELS[repr_][0].format(rb=tile or COEF_K_DEFAULT)
+    roofline = dict(hbm, bound="hbm")
+    if repr_ != 1:
         # coefficients: 48 B and 401-469 flop per update (8.4-9.8 flop/B), at or
         # below the ridge of the FP32 vector units over HBM (78.6 / 8.0 =
         # 9.8 flop/B), so the roofline bound is HBM; the vector-ALU figures go
         # alongside
-        flops = COEF_FLOPS_PER_LU[a.tile or COEF_K_DEFAULT]
+        flops = COEF_FLOPS_PER_LU[tile or COEF_K_DEFAULT]
         tflops = flops * cells / avg_kernel_s / 1e12
-        roofline = dict(hbm, bound="hbm")
         roofline["alu"] = {"achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": tflops / FP32_VALU_PEAK_TFLOPS, "flops_per_update": flops}
     roofline.update({"kernel": kernel, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches,
@@ -370,14 +414,15 @@ def main():
             "algorithmic_bytes_per_update": bytes_per_lu,
             "representation": {1: "populations", 2: "H2 coefficients"}[repr_],
             "force_and_lockin": "f64",
+            "tile": tile or (COEF_K_DEFAULT if repr_ != 1 else 1),
+            "autotune_ms_per_step": tile_ms,
         },
         "roofline": roofline,
-        "hbm": hbm,
-        "impedance": [{"tau_omega": s.tau_omega, "R": zz["R"], "X": zz["X"]}
-                      for s, zz in zip(solves, z)],
     }
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(solves[len(solves) // 2].scaled(2, 0), a.cpu_seconds)
+        # a median-size solve of the workload
+        pick = sorted(solves, key=lambda s: s.fluid_cells)[len(solves) // 2]
+        out["cpu_baseline"] = cpu_baseline(pick.scaled(2, 0), a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

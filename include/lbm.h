@@ -103,8 +103,14 @@ enum { LBM_FAR_WALL = 0, LBM_FAR_EQ = 1 };
  * cell describe it exactly; a step then moves 6 values per cell in and out of
  * HBM instead of Q.  After populations are loaded (lbm_set_populations /
  * lbm_set_deviations) the next step reads them directly, so an arbitrary
- * initial state is honoured exactly. */
-enum { LBM_REPR_AUTO = 0, LBM_REPR_POPULATIONS = 1, LBM_REPR_COEFFICIENTS = 2 };
+ * initial state is honoured exactly; that needs a population buffer (Q values
+ * per cell) beside the coefficients.  COEFFICIENTS_NOLOAD keeps the
+ * coefficients without it (48 instead of 196 bytes per cell in FP32): the run
+ * starts from rest, lbm_set_populations / lbm_set_deviations and a
+ * population blob in lbm_set_state return LBM_EINVAL, everything else works
+ * as with COEFFICIENTS (lbm_representation reports LBM_REPR_COEFFICIENTS). */
+enum { LBM_REPR_AUTO = 0, LBM_REPR_POPULATIONS = 1, LBM_REPR_COEFFICIENTS = 2,
+       LBM_REPR_COEFFICIENTS_NOLOAD = 3 };
 
 typedef struct lbm_params {
   uint32_t abi_version;  /* LBM_ABI_VERSION */
@@ -124,7 +130,7 @@ typedef struct lbm_params {
                             H2 coefficients of the regularized post-collision state
                             (regularized collision only; automatic picks 2 when nx >= 64
                             and one coefficient plane, ny x nx rounded up to 64, stays
-                            under 2 GiB) */
+                            under 2 GiB), 3 = as 2 without population loads */
   int32_t nx, ny;        /* domain in cells; nx >= 3 and ny >= 3 */
   int32_t box_x0, box_y0, box_lx, box_ly; /* BOX only; sides and margins >= longest link */
   double tau;            /* relaxation time of the update, > 1/2; +inf allowed (BGK: free streaming) */

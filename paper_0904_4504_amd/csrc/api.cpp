@@ -133,7 +133,9 @@ bool coefficient_plane_fits(const lbm_params* p) {
 
 // Device state kept as the six H2 coefficients (else the Q populations).
 bool uses_coefficients(const lbm_params* p) {
-  if (p->representation == LBM_REPR_COEFFICIENTS) return true;
+  if (p->representation == LBM_REPR_COEFFICIENTS ||
+      p->representation == LBM_REPR_COEFFICIENTS_NOLOAD)
+    return true;
   return p->representation == LBM_REPR_AUTO && p->collision == LBM_COLL_REGULARIZED &&
          p->nx >= kCoefTileW && coefficient_plane_fits(p);
 }
@@ -150,14 +152,14 @@ int validate(const lbm_params* p, HostLattice* lat) {
   if (p->wall == LBM_WALL_MAXWELL && !(p->accommodation >= 0.0 && p->accommodation <= 1.0))
     return LBM_EINVAL;
   if (p->far != LBM_FAR_WALL && p->far != LBM_FAR_EQ) return LBM_EINVAL;
-  if (p->representation > LBM_REPR_COEFFICIENTS) return LBM_EINVAL;
-  if (p->representation == LBM_REPR_COEFFICIENTS && p->collision != LBM_COLL_REGULARIZED)
-    return LBM_EINVAL;
+  if (p->representation > LBM_REPR_COEFFICIENTS_NOLOAD) return LBM_EINVAL;
+  const bool coef_asked = p->representation == LBM_REPR_COEFFICIENTS ||
+                          p->representation == LBM_REPR_COEFFICIENTS_NOLOAD;
+  if (coef_asked && p->collision != LBM_COLL_REGULARIZED) return LBM_EINVAL;
   const int R = lat->R;
   if (p->nx < std::max(3, R) || p->ny < std::max(3, R)) return LBM_EINVAL;
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) return LBM_EINVAL;
-  if (p->representation == LBM_REPR_COEFFICIENTS && !coefficient_plane_fits(p))
-    return LBM_EINVAL;
+  if (coef_asked && !coefficient_plane_fits(p)) return LBM_EINVAL;
   // tile: cells per thread of the population kernel, or tile variant of the
   // coefficient kernel
   if (uses_coefficients(p)) {
@@ -343,6 +345,7 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
     lay->buf_elems = lay->qs * L.Q;
   }
   lay->mom = uses_coefficients(p);
+  lay->loadable = !(lay->mom && p->representation == LBM_REPR_COEFFICIENTS_NOLOAD);
   if (lay->mom) {
     lay->coef_k = p->tile ? (int32_t)p->tile : kCoefKDefault;
     const int th = coef_tile_rows(lay->coef_k);
@@ -386,12 +389,13 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   lay->off_fcells = take(sizeof(ForceCell) * ft.cells.size());
   lay->off_drive = take(sizeof(Drive) * (uint64_t)p->max_steps);
   lay->off_hist = take(sizeof(double) * 2 * (uint64_t)lay->hist_cap);
-  lay->buf_bytes = (uint64_t)lay->buf_elems * es;
+  // a coefficient solver that cannot load populations has no population buffer
+  lay->buf_bytes = lay->loadable ? (uint64_t)lay->buf_elems * es : 0;
   o = align_up(o, 4096);
-  lay->off_buf[0] = take(lay->buf_bytes);
+  lay->off_buf[0] = lay->loadable ? take(lay->buf_bytes) : 0;
   if (lay->mom) {
-    // one population buffer (a loaded state, read by the next step) and two
-    // coefficient buffers
+    // one population buffer (a loaded state, read by the next step; none
+    // without loads) and two coefficient buffers
     lay->off_buf[1] = lay->off_buf[0];
     o = align_up(o, 4096);
     lay->off_mbuf[0] = take(lay->mbuf_bytes);
@@ -418,8 +422,10 @@ int init_solver(lbm_solver* s) {
 
   SolveDesc& d = s->desc;
   std::memset(&d, 0, sizeof(d));
-  s->bufs[0] = d.buf[0] = b + lay.off_buf[0];
-  s->bufs[1] = d.buf[1] = b + lay.off_buf[1];
+  if (lay.loadable) {
+    s->bufs[0] = d.buf[0] = b + lay.off_buf[0];
+    s->bufs[1] = d.buf[1] = b + lay.off_buf[1];
+  }
   d.drive = reinterpret_cast<const Drive*>(b + lay.off_drive);
   d.hist = reinterpret_cast<double*>(b + lay.off_hist);
   d.state = reinterpret_cast<SolveState*>(b + lay.off_state);
@@ -520,7 +526,8 @@ int init_solver(lbm_solver* s) {
 
   if ((rc = hip_rc(hipMemsetAsync(b + lay.off_hist, 0, sizeof(double) * 2 * lay.hist_cap, st))))
     return rc;
-  if ((rc = hip_rc(hipMemsetAsync(b + lay.off_buf[0], 0, lay.buf_bytes, st)))) return rc;
+  if (lay.loadable && (rc = hip_rc(hipMemsetAsync(b + lay.off_buf[0], 0, lay.buf_bytes, st))))
+    return rc;
   if (!lay.mom && (rc = hip_rc(hipMemsetAsync(b + lay.off_buf[1], 0, lay.buf_bytes, st))))
     return rc;
   return hip_rc(hipStreamSynchronize(st));
@@ -874,6 +881,7 @@ int copy_in(lbm_solver* s, const double* host, uint64_t n, bool with_rest) {
   const lbm_params& p = s->p;
   const int Q = s->lat.Q;
   if (n != (uint64_t)Q * p.ny * p.nx) return LBM_EINVAL;
+  if (!s->lay.loadable) return LBM_EINVAL;  // no population buffer to load into
   if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHIP;
   const bool f64 = p.storage == LBM_STORE_F64;
   std::vector<char> stage(s->lay.buf_bytes, 0);
@@ -973,7 +981,8 @@ int lbm_set_state(lbm_solver* s, const void* host, uint64_t bytes) {
   StateHeader h;
   std::memcpy(&h, host, sizeof(h));
   if (h.magic != kStateMagic || h.lattice != s->p.lattice || h.storage != s->p.storage ||
-      h.nx != s->p.nx || h.ny != s->p.ny || (h.coeffs && !s->lay.mom))
+      h.nx != s->p.nx || h.ny != s->p.ny || (h.coeffs && !s->lay.mom) ||
+      (!h.coeffs && !s->lay.loadable))
     return LBM_EINVAL;
   const uint64_t payload = h.coeffs ? s->lay.mbuf_bytes : s->lay.buf_bytes;
   if (h.bytes != payload || bytes != sizeof(h) + payload) return LBM_EINVAL;

@@ -44,6 +44,7 @@ struct Layout {
   // coefficient representation (mom): six coefficient planes, updated in
   // tiles of kCoefTileW columns x coef_tile_rows(coef_k) rows
   bool mom = false;
+  bool loadable = true;  // has the population buffer a populations load needs
   int32_t coef_k = 0, tiles_x = 0, mntiles = 0;
   int64_t mpitch = 0, mks = 0;
   uint64_t mbuf_bytes = 0, off_mwork = 0, off_mbuf[2] = {0, 0};

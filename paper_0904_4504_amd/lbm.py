@@ -21,7 +21,7 @@ STORE_F64, STORE_F32_DEV = 0, 1
 COLL_REGULARIZED, COLL_BGK = 0, 1
 WALL_BB, WALL_DS, WALL_MAXWELL = 0, 1, 2
 GEOM_PLATE, GEOM_BOX, GEOM_PERIODIC = 0, 1, 2
-REPR_AUTO, REPR_POPULATIONS, REPR_COEFFICIENTS = 0, 1, 2
+REPR_AUTO, REPR_POPULATIONS, REPR_COEFFICIENTS, REPR_COEFFICIENTS_NOLOAD = 0, 1, 2, 3
 FAR_WALL, FAR_EQ = 0, 1
 
 # every symbol include/lbm.h declares
@@ -134,10 +134,24 @@ def default_params():
     return p
 
 
-def params_from_solve(s, history_capacity=0, tile=0, representation=REPR_AUTO):
-    """lbm_params for an lbm_inputs.Solve."""
+def keeps_coefficients(s):
+    """True if the automatic representation keeps this solve as H2
+    coefficients: regularized collision, nx >= 64 and one coefficient plane
+    (ny x nx rounded up to 64) below 2 GiB -- the library's rule."""
+    es = 8 if s.storage == "f64" else 4
+    return (s.collision == "regularized" and s.nx >= 64
+            and s.ny * ((s.nx + 63) // 64 * 64) * es < 2 ** 31)
+
+
+def params_from_solve(s, history_capacity=0, tile=0, representation=REPR_AUTO, loads=True):
+    """lbm_params for an lbm_inputs.Solve.  loads=False: a solve that will not
+    load populations and that the automatic representation keeps as
+    coefficients is created without the population buffer
+    (REPR_COEFFICIENTS_NOLOAD)."""
     p = default_params()
     p.tile = tile
+    if not loads and representation == REPR_AUTO and keeps_coefficients(s):
+        representation = REPR_COEFFICIENTS_NOLOAD
     p.representation = representation
     p.lattice = s.Q
     p.storage = STORE_F64 if s.storage == "f64" else STORE_F32_DEV

@@ -111,7 +111,8 @@ def _box(**kw):
     (_box, {"box_x0": 2}, B.EINVAL),
     (_box, {"box_lx": 2}, B.EINVAL),
     (_box, {"box_x0": 128 - 32 - 2}, B.EINVAL),
-    (_box, {"representation": 3}, B.EINVAL),
+    (_box, {"representation": 4}, B.EINVAL),
+    (_box, {"representation": B.REPR_COEFFICIENTS_NOLOAD, "collision": B.COLL_BGK}, B.EINVAL),
     (_box, {"representation": B.REPR_COEFFICIENTS, "collision": B.COLL_BGK}, B.EINVAL),
     (_box, {"wall": B.WALL_DS}, B.EINVAL),
     (_box, {"wall": B.WALL_MAXWELL, "accommodation": 0.5}, B.EINVAL),
@@ -142,6 +143,18 @@ def test_required_bytes_sizes():
     assert P.required_bytes(p) >= 2 * 37 * cells * 8
     p.tau = float("inf")
     P.required_bytes(p)
+    # coefficients without population loads: the two coefficient buffers only
+    p = _box(representation=B.REPR_COEFFICIENTS_NOLOAD)
+    n = P.required_bytes(p)
+    assert 12 * cells * 4 <= n < 12 * cells * 4 * 1.2 + 1e6
+
+
+def test_params_without_loads_pick_the_coefficient_buffer_only():
+    s = W.beam_box(1.0, n=128).scaled(100, 50)
+    assert P.params_from_solve(s, loads=False).representation == B.REPR_COEFFICIENTS_NOLOAD
+    assert P.params_from_solve(s).representation == B.REPR_AUTO
+    narrow = W.plate_sweep(1.0, ny=64).scaled(100, 50)
+    assert P.params_from_solve(narrow, loads=False).representation == B.REPR_AUTO
 
 
 def test_diffuse_and_maxwell_walls_on_a_plate_are_accepted():
@@ -157,7 +170,7 @@ def test_beam_box_fits_one_gpu_with_room():
 
 
 def test_strerror():
-    for code in (B.OK, B.EINVAL, B.ENOMEM, B.EHIP, B.ERANGE, B.EUNSTABLE, B.EABI):
+    for code in (B.OK, B.EINVAL, B.ENOMEM, B.EHIP, B.ERANGE, B.EUNSTABLE, B.EABI, B.ESCRATCH):
         assert P.strerror(code) and P.strerror(code) != "unknown error"
     assert P.strerror(-99) == "unknown error"
 

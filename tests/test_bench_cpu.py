@@ -16,7 +16,7 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert "one GPU" in r.stderr
 
 
-@pytest.mark.parametrize("name", ["beam_box", "plate_sweep"])
+@pytest.mark.parametrize("name", ["batch", "beam_box", "plate_sweep"])
 def test_workload_window_is_the_timed_steps(name):
     """The lock-in window is exactly the K timed steps after the warmup; the
     solves have room for the second (kernel-timing) pass after it."""
