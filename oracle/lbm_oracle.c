@@ -46,6 +46,18 @@
  *     the population of (vx, -vy) that crossed the wall from column x - vx
  *     at the mirror row (reflected in y only; its tangential velocity, and
  *     so the wall's tangential motion, does not enter).
+ *   - Diffuse and Maxwell walls on the box: a link belongs to the face on
+ *     whose axis its arrival cell lies outside the body's range (a corner
+ *     link, outside on both axes, keeps bounce-back).  A face is cut into
+ *     columns, one per arrival coordinate along it.  The diffuse wall emits
+ *     into every link of a column the H2 equilibrium at the wall velocity
+ *     times the column's wall density, which returns to the fluid the mass
+ *     bounce-back would return through those links (the crossing mass, plus
+ *     on the faces normal to the motion the mass the moving face displaces;
+ *     on a plate this is the zero-normal-flux rule above).  The specular
+ *     image is the population that left the source point reflected through
+ *     the face plane, with the velocity's normal component reversed; on the
+ *     faces normal to the motion it carries the moving-wall term.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -80,14 +92,15 @@ typedef struct {
   double u0;      /* drive amplitude: U_w(t) = u0 sin(omega t) along x */
   double rho0;    /* rest density */
   int nthreads;   /* OpenMP threads, 0 = runtime default */
-  int wall;       /* ORC_WALL_*: model of the moving wall (DS, MAXWELL: plate only) */
+  int wall;       /* ORC_WALL_*: model of the moving wall or body (plate or box) */
   double sigma;   /* MAXWELL: tangential momentum accommodation, 0 (specular) .. 1 (DS) */
 } oracle_params;
 
 typedef struct {
   int Q;
   int vx[ORC_MAXQ], vy[ORC_MAXQ], opp[ORC_MAXQ];
-  int refl[ORC_MAXQ];  /* index of (vx, -vy): the specular image */
+  int refl[ORC_MAXQ];  /* index of (vx, -vy): the specular image in y */
+  int reflx[ORC_MAXQ]; /* index of (-vx, vy): the specular image in x */
   real w[ORC_MAXQ];
   real theta;
 } lattice;
@@ -116,9 +129,12 @@ static int load_lattice(int Q, lattice* L) {
       if (v[j][0] == -v[i][0] && v[j][1] == -v[i][1]) L->opp[i] = j;
     if (L->opp[i] < 0) return -1;
     L->refl[i] = -1;
-    for (int j = 0; j < Q; ++j)
+    L->reflx[i] = -1;
+    for (int j = 0; j < Q; ++j) {
       if (v[j][0] == v[i][0] && v[j][1] == -v[i][1]) L->refl[i] = j;
-    if (L->refl[i] < 0) return -1;
+      if (v[j][0] == -v[i][0] && v[j][1] == v[i][1]) L->reflx[i] = j;
+    }
+    if (L->refl[i] < 0 || L->reflx[i] < 0) return -1;
   }
   return 0;
 }
@@ -155,9 +171,9 @@ static int check_params(const oracle_params* p, const lattice* L) {
   } else if (p->geometry != ORC_GEOM_PERIODIC) {
     return -1;
   }
-  if (p->wall == ORC_WALL_DS) return p->geometry == ORC_GEOM_PLATE ? 0 : -1;
-  if (p->wall == ORC_WALL_MAXWELL)
-    return p->geometry == ORC_GEOM_PLATE && p->sigma >= 0 && p->sigma <= 1 ? 0 : -1;
+  const int walled = p->geometry == ORC_GEOM_PLATE || p->geometry == ORC_GEOM_BOX;
+  if (p->wall == ORC_WALL_DS) return walled ? 0 : -1;
+  if (p->wall == ORC_WALL_MAXWELL) return walled && p->sigma >= 0 && p->sigma <= 1 ? 0 : -1;
   return p->wall == ORC_WALL_BB ? 0 : -1;
 }
 
@@ -188,6 +204,68 @@ static void wall_density(const oracle_params* p, const lattice* L, const real* f
       for (int r = 0; r < -L->vy[i]; ++r) m += F_AT(f, x, r, i);
     rho_w[x] = m / emit;
   }
+}
+
+/* Face of a box link by its arrival cell (x, y): 0 below the body, 1 above,
+ * 2 left of it, 3 right of it; -1 for a corner link.  Column of the link on
+ * its face: faces 0, 1 by x, faces 2, 3 by y, numbered face after face. */
+static int box_face(const oracle_params* p, int x, int y) {
+  const int x0 = p->box_x0, x1 = p->box_x0 + p->box_lx;
+  const int y0 = p->box_y0, y1 = p->box_y0 + p->box_ly;
+  const int inx = x >= x0 && x < x1, iny = y >= y0 && y < y1;
+  if (inx && !iny) return y < y0 ? 0 : 1;
+  if (iny && !inx) return x < x0 ? 2 : 3;
+  return -1;
+}
+
+static int box_column(const oracle_params* p, int face, int x, int y) {
+  const int lx = p->box_lx, ly = p->box_ly;
+  switch (face) {
+    case 0: return x - p->box_x0;
+    case 1: return lx + x - p->box_x0;
+    case 2: return 2 * lx + y - p->box_y0;
+    default: return 2 * lx + ly + y - p->box_y0;
+  }
+}
+
+/* Bounce-back mirror cell of the box link arriving at (x, y) from source
+ * (sx, sy) in the body: per axis, through the face plane when the arrival
+ * lies outside the body's range on that axis, else the arrival coordinate. */
+static void box_mirror(const oracle_params* p, int x, int y, int sx, int sy, int* px, int* py) {
+  const int x0 = p->box_x0, x1 = p->box_x0 + p->box_lx;
+  const int y0 = p->box_y0, y1 = p->box_y0 + p->box_ly;
+  *px = x < x0 ? 2 * x0 - 1 - sx : (x >= x1 ? 2 * x1 - 1 - sx : x);
+  *py = y < y0 ? 2 * y0 - 1 - sy : (y >= y1 ? 2 * y1 - 1 - sy : y);
+}
+
+/* Wall density of every face column of the box: the mass bounce-back would
+ * deliver through the column's links (each reflected population plus its
+ * moving-wall term) over the mass the wall emits per unit density through
+ * them, sum over the links of w_i times the equilibrium factor. */
+static void box_wall_density(const oracle_params* p, const lattice* L, const real* f, real U,
+                             real* rho_w) {
+  const int m = vmax_of(L);
+  const int ncol = 2 * (p->box_lx + p->box_ly);
+  real* num = (real*)calloc((size_t)ncol, sizeof(real));
+  real* den = (real*)calloc((size_t)ncol, sizeof(real));
+  for (int y = p->box_y0 - m; y < p->box_y0 + p->box_ly + m; ++y)
+    for (int x = p->box_x0 - m; x < p->box_x0 + p->box_lx + m; ++x) {
+      if (in_body(p, x, y)) continue;
+      const int face = box_face(p, x, y);
+      if (face < 0) continue;
+      const int c = box_column(p, face, x, y);
+      for (int i = 0; i < L->Q; ++i) {
+        const int sx = x - L->vx[i], sy = y - L->vy[i];
+        if (!in_body(p, sx, sy)) continue;
+        int px, py;
+        box_mirror(p, x, y, sx, sy, &px, &py);
+        num[c] += F_AT(f, px, py, L->opp[i]) + 2 * L->w[i] * (real)p->rho0 * (L->vx[i] * U) / L->theta;
+        den[c] += L->w[i] * eq_factor(L, i, U);
+      }
+    }
+  for (int c = 0; c < ncol; ++c) rho_w[c] = den[c] != 0 ? num[c] / den[c] : 0;
+  free(num);
+  free(den);
 }
 
 static real advect_one(const oracle_params* p, const lattice* L, const real* f, int x, int y,
@@ -231,15 +309,28 @@ static real advect_one(const oracle_params* p, const lattice* L, const real* f, 
   /* box inside a rest-equilibrium far field */
   if (sx < 0 || sx >= p->nx || sy < 0 || sy >= p->ny) return rest;
   if (in_body(p, sx, sy)) {
-    const int x0 = p->box_x0, x1 = p->box_x0 + p->box_lx;
-    const int y0 = p->box_y0, y1 = p->box_y0 + p->box_ly;
-    int px = x, py = y;
-    if (x < x0) px = 2 * x0 - 1 - sx;
-    else if (x >= x1) px = 2 * x1 - 1 - sx;
-    if (y < y0) py = 2 * y0 - 1 - sy;
-    else if (y >= y1) py = 2 * y1 - 1 - sy;
-    real fr = F_AT(f, px, py, L->opp[i]);
-    real fa = fr + 2 * L->w[i] * (real)p->rho0 * (vx * U) / L->theta;
+    int px, py;
+    box_mirror(p, x, y, sx, sy, &px, &py);
+    const real fr = F_AT(f, px, py, L->opp[i]);
+    const real ladd = 2 * L->w[i] * (real)p->rho0 * (vx * U) / L->theta;
+    const int face = box_face(p, x, y);
+    real fa;
+    if (!rho_w || face < 0) {
+      fa = fr + ladd; /* bounce-back wall, or a corner link */
+    } else {
+      fa = L->w[i] * rho_w[box_column(p, face, x, y)] * eq_factor(L, i, U);
+      if (p->wall == ORC_WALL_MAXWELL) {
+        /* specular part: the population that left the source point
+           reflected through the face plane, normal velocity reversed; the
+           faces normal to the motion add the moving-wall term */
+        real sp;
+        if (face <= 1)
+          sp = F_AT(f, sx, py, L->refl[i]);
+        else
+          sp = F_AT(f, px, sy, L->reflx[i]) + ladd;
+        fa = (real)p->sigma * fa + (1 - (real)p->sigma) * sp;
+      }
+    }
     *fx -= vx * (fr + fa);
     *fy -= vy * (fr + fa);
     return fa;
@@ -331,6 +422,11 @@ int oracle_collide(int Q, int collision, double tau, const double* fin, double* 
   return 0;
 }
 
+/* Columns of the diffuse / Maxwell wall: the plate's nx, the box's perimeter. */
+static int wall_columns(const oracle_params* p) {
+  return p->geometry == ORC_GEOM_BOX ? 2 * (p->box_lx + p->box_ly) : p->nx;
+}
+
 static real* import_f(const oracle_params* p, const lattice* L, const double* f0) {
   size_t n = (size_t)p->nx * p->ny * L->Q;
   real* f = (real*)malloc(n * sizeof(real));
@@ -365,9 +461,10 @@ int oracle_advect(const oracle_params* p, const double* f_in, double U, double* 
   if (!f) return -2;
   real* rho_w = NULL;
   if (p->wall == ORC_WALL_DS || p->wall == ORC_WALL_MAXWELL) {
-    rho_w = (real*)malloc(sizeof(real) * p->nx);
+    rho_w = (real*)malloc(sizeof(real) * (size_t)wall_columns(p));
     if (!rho_w) { free(f); return -2; }
-    wall_density(p, &L, f, (real)U, rho_w);
+    if (p->geometry == ORC_GEOM_BOX) box_wall_density(p, &L, f, (real)U, rho_w);
+    else wall_density(p, &L, f, (real)U, rho_w);
   }
   real Fx = 0, Fy = 0;
   for (int y = 0; y < p->ny; ++y)
@@ -399,7 +496,7 @@ int oracle_run(const oracle_params* p, const double* f0, long nsteps, double* fx
   real* rowfx = (real*)calloc((size_t)p->ny, sizeof(real));
   real* rowfy = (real*)calloc((size_t)p->ny, sizeof(real));
   const int diffuse = p->wall == ORC_WALL_DS || p->wall == ORC_WALL_MAXWELL;
-  real* rho_w = diffuse ? (real*)calloc((size_t)p->nx, sizeof(real)) : NULL;
+  real* rho_w = diffuse ? (real*)calloc((size_t)wall_columns(p), sizeof(real)) : NULL;
   if (!f || !g || !rowfx || !rowfy || (diffuse && !rho_w)) {
     free(f); free(g); free(rowfx); free(rowfy); free(rho_w);
     return -2;
@@ -410,7 +507,10 @@ int oracle_run(const oracle_params* p, const double* f0, long nsteps, double* fx
 #endif
   for (long n = 0; n < nsteps; ++n) {
     const real U = (real)(p->u0 * sin(p->omega * ((double)n + 0.5)));
-    if (rho_w) wall_density(p, &L, f, U, rho_w);
+    if (rho_w) {
+      if (p->geometry == ORC_GEOM_BOX) box_wall_density(p, &L, f, U, rho_w);
+      else wall_density(p, &L, f, U, rho_w);
+    }
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < p->ny; ++y) {
       real Fx = 0, Fy = 0;

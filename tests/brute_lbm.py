@@ -33,12 +33,27 @@ def _reflect_box(p, d, box):
     return tuple(a)
 
 
+def _box_side(p, box):
+    """Face a population leaving fluid cell p towards the body hits: 'b',
+    't' (below, above: p within the body's x range), 'l', 'r' (left, right:
+    within its y range), or None (outside both ranges: a corner)."""
+    x0, y0, lx, ly = box
+    inx = x0 <= p[0] < x0 + lx
+    iny = y0 <= p[1] < y0 + ly
+    if inx and not iny:
+        return "b" if p[1] < y0 else "t"
+    if iny and not inx:
+        return "l" if p[0] < x0 else "r"
+    return None
+
+
 def stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse=False, sigma=1.0):
     """Push streaming.  Returns (f_adv, Fx, Fy); f is [q][y][x].  With
-    diffuse=True the plate wall re-emits what hits it as the H2 equilibrium at
-    the wall velocity, at the density that returns the column's mass; with
-    sigma < 1 only that fraction is re-emitted diffusely and the rest of each
-    particle is reflected specularly (v_y -> -v_y, v_x kept)."""
+    diffuse=True the plate wall, or each face of the box, re-emits what hits
+    it as the H2 equilibrium at the wall velocity, at the density that returns
+    the column's mass; with sigma < 1 only that fraction is re-emitted
+    diffusely and the rest of each particle is reflected specularly (the
+    normal velocity reversed); the box's corners keep bounce-back."""
     Q, ny, nx = f.shape
     opp = [int(np.flatnonzero((v[:, 0] == -v[i, 0]) & (v[:, 1] == -v[i, 1]))[0]) for i in range(Q)]
     refl = [int(np.flatnonzero((v[:, 0] == v[i, 0]) & (v[:, 1] == -v[i, 1]))[0]) for i in range(Q)]
@@ -54,8 +69,8 @@ def stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse=False, sigma=1.0
 
     # diffuse plate wall: mass hitting the wall per column, and emitted shape
     hit = np.zeros(nx)
-    emitted = {}
-    if diffuse:
+    box_hits = []  # (q, departure, destination, bounce-back arrival, value, bounce-back out)
+    if diffuse and geometry == "plate":
         for q in range(Q):
             for y in range(ny):
                 if y + v[q, 1] < 0:
@@ -106,12 +121,56 @@ def stream(f, v, w, theta, geometry, far, box, U, rho0, diffuse=False, sigma=1.0
                         i = opp[q]
                         ax, ay = _reflect_box((x, y), (dx, dy), box)
                         out = val + 2 * w[i] * rho0 * (v[i, 0] * U) / theta
+                        if diffuse and _box_side((x, y), box) is not None:
+                            box_hits.append((q, x, y, dx, dy, ax, ay, val, out))
+                            continue
                         fadv[i, ay, ax] = out
                         Fx += -v[i, 0] * (val + out)
                         Fy += -v[i, 1] * (val + out)
                         continue
                     fadv[q, dy, dx] = val
-    if diffuse:
+    if diffuse and geometry == "box":
+        # box faces: a population that hits a face (its departure beside the
+        # body on one axis only) is gathered per face column -- the column
+        # of the cell bounce-back would send it to -- with the mass
+        # bounce-back would deliver; the diffuse share of each column goes
+        # out as the H2 equilibrium at the wall velocity in the bounce-back
+        # directions, the specular share goes to the destination mirrored
+        # through the face plane with the normal velocity reversed (plus the
+        # moving-wall term on the faces normal to the motion)
+        vu = v[:, 0] * U
+        eq = 1 + vu / theta + vu ** 2 / (2 * theta ** 2) - U ** 2 / (2 * theta)
+        refx = [int(np.flatnonzero((v[:, 0] == -v[i, 0]) & (v[:, 1] == v[i, 1]))[0])
+                for i in range(Q)]
+        mass, shape = {}, {}
+        for q, x, y, dx, dy, ax, ay, val, out in box_hits:
+            key = (_box_side((x, y), box), ax if _box_side((x, y), box) in "bt" else ay)
+            mass[key] = mass.get(key, 0.0) + out
+            shape[key] = shape.get(key, 0.0) + w[opp[q]] * eq[opp[q]]
+        arrivals = np.zeros_like(f)
+        for q, x, y, dx, dy, ax, ay, val, out in box_hits:
+            side = _box_side((x, y), box)
+            key = (side, ax if side in "bt" else ay)
+            i = opp[q]
+            arrivals[i, ay, ax] += sigma * w[i] * mass[key] / shape[key] * eq[i]
+            x0, y0, lx, ly = box
+            if side in "bt":
+                plane = y0 if side == "b" else y0 + ly
+                j, mx, my = refl[q], dx, 2 * plane - 1 - dy
+                extra = 0.0
+            else:
+                plane = x0 if side == "l" else x0 + lx
+                j, mx, my = refx[q], 2 * plane - 1 - dx, dy
+                extra = 2 * w[j] * rho0 * (v[j, 0] * U) / theta
+            arrivals[j, my, mx] += (1 - sigma) * (val + extra)
+            Fx += v[q, 0] * val
+            Fy += v[q, 1] * val
+        for q, x, y, dx, dy, ax, ay, val, out in box_hits:
+            i = opp[q]
+            fadv[i, ay, ax] = arrivals[i, ay, ax]
+            Fx -= v[i, 0] * arrivals[i, ay, ax]
+            Fy -= v[i, 1] * arrivals[i, ay, ax]
+    if diffuse and geometry == "plate":
         for i in range(Q):
             for y in range(ny):
                 if y < v[i, 1]:  # arrival rows of the wall
