@@ -70,18 +70,27 @@ enum { LBM_STORE_F64 = 0, LBM_STORE_F32_DEV = 1 };
  * f_i = f_i^eq + (1 - 1/tau)(f_i^adv - f_i^eq) (eq. LBGK, for checks). */
 enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
 
-/* Wall model of the moving body: bounce-back (eq. BB), or diffuse
- * scattering (eq. DS; plate geometry only): a population arriving from the
- * moving wall in column x is the H2 equilibrium (eq. feq_h2) at the wall
- * velocity with the wall density rho_w(x) that balances the mass of the
- * populations of column x crossing the wall in that step (zero normal mass
- * flux, eq. kinetic_bc; the crossing populations are those bounce-back
- * would reflect into column x).  Maxwell wall (plate only): a fraction
- * `accommodation` (sigma_v of Sec. 3, 0..1) of every arrival is the diffuse
- * one and the rest the specular image -- the population of (vx, -vy) that
- * crossed the wall from column x - vx at the mirror row, reflected in y
- * only; 1 is the diffuse wall, 0 specular reflection (no shear).  The
- * stationary far wall stays bounce-back. */
+/* Wall model of the moving plate or body: bounce-back (eq. BB), or diffuse
+ * scattering (eq. DS): a population arriving from the moving wall in column
+ * x is the H2 equilibrium (eq. feq_h2) at the wall velocity with the wall
+ * density rho_w(x) that balances the mass of the populations of column x
+ * crossing the wall in that step (zero normal mass flux, eq. kinetic_bc; the
+ * crossing populations are those bounce-back would reflect into column x).
+ * Maxwell wall: a fraction `accommodation` (sigma_v of Sec. 3, 0..1) of
+ * every arrival is the diffuse one and the rest the specular image -- the
+ * population of (vx, -vy) that crossed the wall from column x - vx at the
+ * mirror row, reflected in y only; 1 is the diffuse wall, 0 specular
+ * reflection (no shear).  On a box each link belongs to the face on whose
+ * axis its arrival cell lies outside the body (links outside it on both axes,
+ * at the corners, keep bounce-back); a face is cut into columns, one per
+ * arrival coordinate along it; a diffuse column returns the mass bounce-back
+ * would return through its links (on the faces normal to the motion this
+ * includes the mass the moving face displaces); the specular image is the
+ * population that left the source point mirrored through the face plane with
+ * its normal velocity reversed, plus the moving-wall term on the faces normal
+ * to the motion.  A box with diffuse or Maxwell faces is kept as populations
+ * and has at most 1024 face columns (2 (box_lx + box_ly)).  The stationary
+ * far wall of a plate stays bounce-back. */
 enum { LBM_WALL_BB = 0, LBM_WALL_DS = 1, LBM_WALL_MAXWELL = 2 };
 
 /* Geometry.
@@ -117,7 +126,7 @@ typedef struct lbm_params {
   uint32_t lattice;      /* LBM_D2Q9 or LBM_D2Q37 */
   uint32_t storage;      /* LBM_STORE_* */
   uint32_t collision;    /* LBM_COLL_* */
-  uint32_t wall;         /* LBM_WALL_BB, or LBM_WALL_DS / LBM_WALL_MAXWELL (plate only) */
+  uint32_t wall;         /* LBM_WALL_BB, LBM_WALL_DS or LBM_WALL_MAXWELL (plate or box) */
   uint32_t geometry;     /* LBM_GEOM_* */
   uint32_t far;          /* LBM_FAR_* */
   uint32_t tile;         /* kernel tile.  Populations: 0 (= 1), 1, 2 or 4; one workgroup of

@@ -119,6 +119,18 @@ def beam_box(tau_omega, n=1024, lx=32, ly=16, period=1024, transient_periods=10,
                  storage=storage, tau_omega=tau_omega, name=f"beam_box_tw{tau_omega:g}")
 
 
+def wall_box(tau_omega, wall, accommodation=1.0, n=256, lx=32, ly=16, period=1024,
+             transient_periods=10, window_periods=10, storage="f32dev"):
+    """The beam-box body with a diffuse ("ds") or Maxwell ("maxwell",
+    accommodation 0..1) surface in a smaller n x n domain."""
+    s = beam_box(tau_omega, n=n, lx=lx, ly=ly, period=period,
+                 transient_periods=transient_periods, window_periods=window_periods,
+                 storage=storage)
+    tag = wall if wall == "ds" else f"{wall}{accommodation:g}"
+    return dataclasses.replace(s, wall=wall, accommodation=accommodation,
+                               name=f"wall_box_{tag}_tw{tau_omega:g}")
+
+
 def batch_sweep(count=256, seed=4, period=1024, transient_periods=10, window_periods=10,
                 side_min=256, side_max=2048):
     """Uneven solves drawn from one PCG64 stream in a fixed order:

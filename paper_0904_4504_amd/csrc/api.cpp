@@ -136,8 +136,10 @@ bool uses_coefficients(const lbm_params* p) {
   if (p->representation == LBM_REPR_COEFFICIENTS ||
       p->representation == LBM_REPR_COEFFICIENTS_NOLOAD)
     return true;
+  // a box with diffuse or Maxwell faces is kept as populations
   return p->representation == LBM_REPR_AUTO && p->collision == LBM_COLL_REGULARIZED &&
-         p->nx >= kCoefTileW && coefficient_plane_fits(p);
+         p->nx >= kCoefTileW && coefficient_plane_fits(p) &&
+         !(p->geometry == LBM_GEOM_BOX && p->wall != LBM_WALL_BB);
 }
 
 int validate(const lbm_params* p, HostLattice* lat) {
@@ -148,7 +150,7 @@ int validate(const lbm_params* p, HostLattice* lat) {
   if (p->collision != LBM_COLL_REGULARIZED && p->collision != LBM_COLL_BGK) return LBM_EINVAL;
   if (p->wall != LBM_WALL_BB && p->wall != LBM_WALL_DS && p->wall != LBM_WALL_MAXWELL)
     return LBM_EINVAL;
-  if (p->wall != LBM_WALL_BB && p->geometry != LBM_GEOM_PLATE) return LBM_EINVAL;
+  if (p->wall != LBM_WALL_BB && p->geometry == LBM_GEOM_PERIODIC) return LBM_EINVAL;
   if (p->wall == LBM_WALL_MAXWELL && !(p->accommodation >= 0.0 && p->accommodation <= 1.0))
     return LBM_EINVAL;
   if (p->far != LBM_FAR_WALL && p->far != LBM_FAR_EQ) return LBM_EINVAL;
@@ -156,6 +158,11 @@ int validate(const lbm_params* p, HostLattice* lat) {
   const bool coef_asked = p->representation == LBM_REPR_COEFFICIENTS ||
                           p->representation == LBM_REPR_COEFFICIENTS_NOLOAD;
   if (coef_asked && p->collision != LBM_COLL_REGULARIZED) return LBM_EINVAL;
+  // a box with diffuse or Maxwell faces: populations only, at most
+  // kMaxWallCols face columns
+  if (p->wall != LBM_WALL_BB && p->geometry == LBM_GEOM_BOX &&
+      (coef_asked || 2 * ((int64_t)p->box_lx + p->box_ly) > kMaxWallCols))
+    return LBM_EINVAL;
   const int R = lat->R;
   if (p->nx < std::max(3, R) || p->ny < std::max(3, R)) return LBM_EINVAL;
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) return LBM_EINVAL;
@@ -237,10 +244,111 @@ struct ForceTables {
   std::vector<ForceCell> cells;
   double fstatic[2] = {0, 0}, kladd[2] = {0, 0};
   double ds[6] = {0, 0, 0, 0, 0, 0};
+  // box with diffuse or Maxwell faces
+  std::vector<WallCol> wcols;
+  std::vector<WallLink> wlinks;
 };
+
+bool diffuse_box(const lbm_params* p) {
+  return p->geometry == LBM_GEOM_BOX && p->wall != LBM_WALL_BB;
+}
+
+// Tables of a box with diffuse or Maxwell faces: its links face column by
+// face column (faces below, above the body by arrival x, left, right of it
+// by arrival y; in a column by arrival cell and direction), then the corner
+// links; per column the lattice sums of its links (long double).  The force
+// is -sum v_l (f_partner + f_arrival) over every link: the rest-state parts
+// give fstatic, the rest is formed per link by the finalize.
+void build_wall_tables(const lbm_params* p, const HostLattice& L, const Layout& lay,
+                       ForceTables* t) {
+  const int R = L.R;
+  const int x0 = p->box_x0, x1 = p->box_x0 + p->box_lx;
+  const int y0 = p->box_y0, y1 = p->box_y0 + p->box_ly;
+  const long double th = L.lw.theta_ld;
+  auto find = [&](int vx, int vy) {
+    for (int j = 0; j < L.Q; ++j)
+      if (L.vx[j] == vx && L.vy[j] == vy) return j;
+    return -1;
+  };
+  auto face_of = [&](int x, int y) {
+    const bool inx = x >= x0 && x < x1, iny = y >= y0 && y < y1;
+    if (inx && !iny) return y < y0 ? 0 : 1;
+    if (iny && !inx) return x < x0 ? 2 : 3;
+    return -1;
+  };
+  long double sx = 0, sy = 0;
+  // the links of a fluid cell, in direction order
+  auto add_cell = [&](int x, int y, int col) {
+    for (int q = 0; q < L.Q; ++q) {
+      const int vx = L.vx[q], vy = L.vy[q];
+      const int sxs = x - vx, sys = y - vy;
+      if (!in_body(p, sxs, sys)) continue;
+      int px, py;
+      mirror_of(p, L, x, y, q, &px, &py);
+      const long double w = L.lw.w_orbit_ld[L.orbit[q]];
+      WallLink l{};
+      l.off_partner = L.opp[q] * lay.qs + py * lay.ys + px;
+      l.col = col;
+      l.w = (double)w;
+      l.vx = vx;
+      l.vy = vy;
+      const int face = face_of(x, y);
+      l.normal = face >= 2;
+      if (face == 0 || face == 1)
+        l.off_spec = find(vx, -vy) * lay.qs + py * lay.ys + sxs;
+      else if (face >= 2)
+        l.off_spec = find(-vx, vy) * lay.qs + sys * lay.ys + px;
+      sx -= 2.0L * w * p->rho0 * vx;
+      sy -= 2.0L * w * p->rho0 * vy;
+      t->wlinks.push_back(l);
+    }
+  };
+  // columns: cells of a face column from the face outwards
+  const int ncol = 2 * (p->box_lx + p->box_ly);
+  t->wcols.assign((size_t)ncol, WallCol{});
+  for (int c = 0; c < ncol; ++c) {
+    int face, at;
+    if (c < p->box_lx) { face = 0; at = x0 + c; }
+    else if (c < 2 * p->box_lx) { face = 1; at = x0 + c - p->box_lx; }
+    else if (c < 2 * p->box_lx + p->box_ly) { face = 2; at = y0 + c - 2 * p->box_lx; }
+    else { face = 3; at = y0 + c - 2 * p->box_lx - p->box_ly; }
+    WallCol& wc = t->wcols[(size_t)c];
+    wc.first = (int32_t)t->wlinks.size();
+    for (int k = 1; k <= R; ++k) {
+      const int x = face <= 1 ? at : (face == 2 ? x0 - k : x1 - 1 + k);
+      const int y = face >= 2 ? at : (face == 0 ? y0 - k : y1 - 1 + k);
+      add_cell(x, y, c);
+    }
+    wc.count = (int32_t)t->wlinks.size() - wc.first;
+    long double mr = 0, z1 = 0, z2 = 0, l1 = 0;
+    for (int i = wc.first; i < wc.first + wc.count; ++i) {
+      const WallLink& l = t->wlinks[(size_t)i];
+      const long double w = L.lw.w_orbit_ld[L.orbit[find((int)l.vx, (int)l.vy)]];
+      const long double vx = l.vx;
+      mr += w;
+      z1 += w * vx / th;
+      z2 += w * (vx * vx / (2 * th * th) - 1 / (2 * th));
+      l1 += 2 * w * vx / th;
+    }
+    wc.Mr = (double)mr;
+    wc.Z1 = (double)z1;
+    wc.Z2 = (double)z2;
+    wc.L1 = (double)l1;
+  }
+  // corner links: cells outside the body's range on both axes, within R
+  for (int y = y0 - R; y < y1 + R; ++y)
+    for (int x = x0 - R; x < x1 + R; ++x)
+      if (!in_body(p, x, y) && face_of(x, y) < 0) add_cell(x, y, -1);
+  t->fstatic[0] = (double)sx;
+  t->fstatic[1] = (double)sy;
+}
 
 void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout& lay,
                         ForceTables* t) {
+  if (diffuse_box(p)) {
+    build_wall_tables(p, L, lay, t);
+    return;
+  }
   long double sx = 0, sy = 0, kx = 0, ky = 0;
   // diffuse or Maxwell wall: a share sigma of every arrival is the diffuse
   // emission, the rest the specular image of a crossing population (the
@@ -387,6 +495,10 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   lay->nfcells = (int32_t)ft.cells.size();
   lay->off_links = take(sizeof(ForceLink) * ft.links.size());
   lay->off_fcells = take(sizeof(ForceCell) * ft.cells.size());
+  lay->nwcols = (int32_t)ft.wcols.size();
+  lay->nwlinks = (int32_t)ft.wlinks.size();
+  lay->off_wcols = take(sizeof(WallCol) * ft.wcols.size());
+  lay->off_wlinks = take(sizeof(WallLink) * ft.wlinks.size());
   lay->off_drive = take(sizeof(Drive) * (uint64_t)p->max_steps);
   lay->off_hist = take(sizeof(double) * 2 * (uint64_t)lay->hist_cap);
   // a coefficient solver that cannot load populations has no population buffer
@@ -432,6 +544,13 @@ int init_solver(lbm_solver* s) {
   d.links = reinterpret_cast<const ForceLink*>(b + lay.off_links);
   d.fcells = reinterpret_cast<const ForceCell*>(b + lay.off_fcells);
   d.nlinks = lay.nlinks;
+  if (lay.nwlinks > 0) {
+    d.wcols = reinterpret_cast<const WallCol*>(b + lay.off_wcols);
+    d.wlinks = reinterpret_cast<const WallLink*>(b + lay.off_wlinks);
+    d.nwcols = lay.nwcols;
+    d.nwlinks = lay.nwlinks;
+  }
+  d.theta = s->lat.lw.theta;
   d.nfcells = lay.nfcells;
   d.qs = lay.qs;
   d.ys = lay.ys;
@@ -509,6 +628,15 @@ int init_solver(lbm_solver* s) {
   if (!ft.cells.empty() &&
       (rc = hip_rc(hipMemcpyAsync(b + lay.off_fcells, ft.cells.data(),
                                   sizeof(ForceCell) * ft.cells.size(), hipMemcpyHostToDevice, st))))
+    return rc;
+  if (!ft.wcols.empty() &&
+      (rc = hip_rc(hipMemcpyAsync(b + lay.off_wcols, ft.wcols.data(),
+                                  sizeof(WallCol) * ft.wcols.size(), hipMemcpyHostToDevice, st))))
+    return rc;
+  if (!ft.wlinks.empty() &&
+      (rc = hip_rc(hipMemcpyAsync(b + lay.off_wlinks, ft.wlinks.data(),
+                                  sizeof(WallLink) * ft.wlinks.size(), hipMemcpyHostToDevice,
+                                  st))))
     return rc;
   if ((rc = hip_rc(hipMemcpyAsync(b + lay.off_drive, drive.data(), sizeof(Drive) * drive.size(),
                                   hipMemcpyHostToDevice, st))))

@@ -48,7 +48,7 @@ namespace lbm {
 template <class L, typename S, bool DSW, int q>
 __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__ fin, int x,
                                        int y, double ladd, double wq, double U, double cm,
-                                       double theta) {
+                                       double theta, int face, int col) {
   constexpr int vx = L::vx[q], vy = L::vy[q];
   constexpr int o = opposite<L>(q);
   const int nx = d.nx, ny = d.ny;
@@ -99,6 +99,25 @@ __device__ __forceinline__ S pull_edge(const SolveDesc& d, const S* __restrict__
     else if (x >= d.bx1) px = 2 * d.bx1 - 1 - sx;
     if (y < d.by0) py = 2 * d.by0 - 1 - sy;
     else if (y >= d.by1) py = 2 * d.by1 - 1 - sy;
+    if (DSW && d.wall == WALL_DS && face >= 0) {
+      // a face link of a diffuse box: the column's diffuse emission (a share
+      // sigma; the rest the specular image -- the population of the velocity
+      // mirrored in the face's normal at the source mirrored through the face
+      // plane, with the moving-wall term on the faces normal to the motion)
+      double e = ds_box_arrival(d.wcols[col], d.rho0, U, cm, wq, (double)vx, theta);
+      if (d.sigma != 1.0) {
+        double sp;
+        if (face <= 1) {
+          constexpr int qr = reflect_y<L>(q);
+          sp = (double)fin[qr * qs + py * ys + sx];
+        } else {
+          constexpr int qr = reflect_x<L>(q);
+          sp = (double)fin[qr * qs + sy * ys + px] + wq * vx * ladd;
+        }
+        e = d.sigma * e + (1.0 - d.sigma) * sp;
+      }
+      return (S)e;
+    }
     return fin[o * qs + py * ys + px] + (S)(wq * vx * ladd);
   }
   return fin[q * qs + sy * ys + sx];
@@ -217,6 +236,43 @@ __device__ __forceinline__ void pull_cell_bb(S (&f)[L::Q], WallMom<S>& wall, con
   });
 }
 
+// Deviation of the mass crossing the face column of fluid cell (x, y) of a
+// diffuse box in this step: the populations of the column (the cells on the
+// fluid side of the face in the cell's row or column, within R of it) whose
+// straight destination lies in the body -- the bounce-back partners of the
+// column's links.
+template <class L, typename S>
+__device__ __forceinline__ double box_cross_mass(const SolveDesc& d, const S* __restrict__ fin,
+                                                 int face, int x, int y) {
+  constexpr int R = L::R;
+  const int64_t qs = d.qs, ys = d.ys;
+  double cm = 0.0;
+  static_for<0, L::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int vx = L::vx[q], vy = L::vy[q];
+    for (int k = 1; k <= R; ++k) {
+      // the column's cell k away from the face, and where its population goes
+      int cx = x, cy = y;
+      bool into = false;
+      if (face == 0) {
+        cy = d.by0 - k;
+        into = vy >= k && x + vx >= d.bx0 && x + vx < d.bx1;
+      } else if (face == 1) {
+        cy = d.by1 - 1 + k;
+        into = -vy >= k && x + vx >= d.bx0 && x + vx < d.bx1;
+      } else if (face == 2) {
+        cx = d.bx0 - k;
+        into = vx >= k && y + vy >= d.by0 && y + vy < d.by1;
+      } else {
+        cx = d.bx1 - 1 + k;
+        into = -vx >= k && y + vy >= d.by0 && y + vy < d.by1;
+      }
+      if (into) cm += (double)fin[q * qs + cy * ys + cx];
+    }
+  });
+  return cm;
+}
+
 // Update of one cell: pull, moments, collision, store.  OUTM stores the six H2 coefficients of the
 // post-collision state (a0, bx, by, cxx, cxy, cyy) to the coefficient planes
 // instead of the Q populations (regularized collision only; used for the first
@@ -256,16 +312,25 @@ __device__ __forceinline__ void update_cell(const SolveDesc& d, const S* __restr
     const double ladd = d.ladd_scale * U;
     // diffuse wall: deviation of the mass crossing the wall in column x
     double cm = 0.0;
+    int face = -1, col = 0;
     if (DSW && d.wall == WALL_DS && d.geom == GEOM_PLATE && y < R)
       static_for<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (L::vy[q] < 0)
           for (int r = 0; r < -L::vy[q]; ++r) cm += (double)fin[q * qs + r * ys + x];
       });
+    if (DSW && d.wall == WALL_DS && d.geom == GEOM_BOX) {
+      face = box_face<R>(d, x, y);
+      if (face >= 0) {
+        col = box_column(d, face, x, y);
+        cm = box_cross_mass<L, S>(d, fin, face, x, y);
+      }
+    }
     if constexpr (DSW) {
       static_for<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        f[q] = pull_edge<L, S, DSW, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], U, cm, lat.theta);
+        f[q] = pull_edge<L, S, DSW, q>(d, fin, x, y, ladd, lat.w[L::orbit[q]], U, cm, lat.theta,
+                                       face, col);
       });
     } else {
       const EdgeGeom g = edge_geom(d);
@@ -410,7 +475,39 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
       for (int k = 0; k < 6; ++k) lk[k] = st->lockin[k];
   }
   double fx = 0.0, fy = 0.0, fm = 0.0;
-  if (coeffs) {
+  if (!coeffs && d.nwlinks > 0) {
+    // box with diffuse or Maxwell faces: every link's arrival as the step
+    // kernel formed it -- the column's diffuse emission from the column's
+    // crossing mass (first pass), mixed with the specular image; corner links
+    // bounce back -- and the momentum exchange -v_l (f_partner + f_arrival)
+    const S* __restrict__ f = static_cast<const S*>(n & 1 ? d.buf[1] : d.buf[0]);
+    __shared__ double cmass[kMaxWallCols];
+    for (int c = threadIdx.x; c < d.nwcols; c += kBlock) {
+      const WallCol col = d.wcols[c];
+      double m = 0.0;
+      for (int k = 0; k < col.count; ++k) m += (double)f[d.wlinks[col.first + k].off_partner];
+      cmass[c] = m;
+    }
+    __syncthreads();
+    const double U = d.drive[n].u;
+    const double ladd = d.ladd_scale * U;
+    for (int i = threadIdx.x; i < d.nwlinks; i += kBlock) {
+      const WallLink l = d.wlinks[i];
+      const double fp = (double)f[l.off_partner];
+      double a;
+      if (l.col < 0) {
+        a = fp + l.w * l.vx * ladd;
+      } else {
+        a = ds_box_arrival(d.wcols[l.col], d.rho0, U, cmass[l.col], l.w, l.vx, d.theta);
+        if (d.sigma != 1.0) {
+          const double sp = (double)f[l.off_spec] + (l.normal ? l.w * l.vx * ladd : 0.0);
+          a = d.sigma * a + (1.0 - d.sigma) * sp;
+        }
+      }
+      fx -= l.vx * (fp + a);
+      fy -= l.vy * (fp + a);
+    }
+  } else if (coeffs) {
     const S* __restrict__ c = static_cast<const S*>(d.mbuf[n & 1]);
     const int64_t ks = d.mks;
     for (int i = threadIdx.x; i < d.nfcells; i += kBlock) {
@@ -455,7 +552,7 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
     }
     fx = d.fstatic[0] + d.kladd[0] * dr.u + sx;
     fy = d.fstatic[1] + d.kladd[1] * dr.u + sy;
-    if (d.wall == WALL_DS) {
+    if (d.wall == WALL_DS && d.geom == GEOM_PLATE) {
       // the diffuse emissions' share of -sum v_i f_i^adv over the links:
       // every column emits w_i rho_w E_i(U) along each link, rho_w from the
       // column's crossing mass (rest part nx rho0 A1, deviation sm)

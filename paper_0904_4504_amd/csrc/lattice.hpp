@@ -61,6 +61,14 @@ constexpr int reflect_y(int i) {
   return -1;
 }
 
+// Index of the specular image in x, (-vx, vy), evaluated at compile time.
+template <class L>
+constexpr int reflect_x(int i) {
+  for (int j = 0; j < L::Q; ++j)
+    if (L::vx[j] == -L::vx[i] && L::vy[j] == L::vy[i]) return j;
+  return -1;
+}
+
 // Quadrature weights per orbit and theta, derived on the host.
 struct LatticeWeights {
   int Q;

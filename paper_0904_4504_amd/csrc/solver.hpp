@@ -57,6 +57,34 @@ struct ForceCell {
   double wx[6], wy[6], wm[6];
 };
 
+// Box with diffuse or Maxwell faces.  A link (arrival cell, direction whose
+// source lies in the body) belongs to the face on whose axis its arrival cell
+// lies outside the body's range; faces are cut into columns (one per arrival
+// coordinate along the face: faces below, above the body by x, left, right of
+// it by y; numbered in that order).  Per column, over its links l: Mr = sum
+// w_l, Z1 = sum w_l vx_l / theta, Z2 = sum w_l (vx_l^2 / 2 theta^2 -
+// 1 / 2 theta) (the mass emitted per unit wall density is Mr + Z1 U + Z2 U^2),
+// L1 = sum 2 w_l vx_l / theta (the moving-wall terms bounce-back would add,
+// per unit rho0 U); the column's links are [first, first + count) of the link
+// table.
+struct WallCol {
+  double Mr, Z1, Z2, L1;
+  int32_t first, count;
+};
+// One link of such a box: its bounce-back partner (the opposite population at
+// the mirror cell) and, on a face, its specular source (the population of
+// the velocity mirrored in the face's normal, at the source point mirrored
+// through the face plane), as element offsets into a population buffer; its
+// column (-1: a corner link, which keeps bounce-back); normal: the face is
+// normal to the motion (x faces); the arrival direction's weight and velocity.
+struct WallLink {
+  int64_t off_partner, off_spec;
+  int32_t col, normal;
+  double w, vx, vy;
+};
+// Most face columns a diffuse or Maxwell box may have (2 (box_lx + box_ly)).
+constexpr int kMaxWallCols = 1024;
+
 // Everything a kernel needs to advance one solve; lives in device memory.
 // Pointers are device addresses.
 struct SolveDesc {
@@ -91,6 +119,11 @@ struct SolveDesc {
   // Bx = sum_{vy>0} vy vx^2 w / th, By0 = sum_{vy>0} vy^2 w,
   // By2 = sum_{vy>0} vy^2 w (vx^2/2th^2 - 1/2th), nx rho0
   double ds[6];
+  // box with diffuse or Maxwell faces (null otherwise)
+  const WallCol* wcols;      // [nwcols]
+  const WallLink* wlinks;    // [nwlinks]
+  int32_t nwcols, nwlinks;
+  double theta;              // lattice theta (the finalize's diffuse emission)
 };
 
 // One entry of the launch work list: a tile of one solve.

@@ -10,6 +10,7 @@ steps plus the last 64 steps in full.
   python tests/golden/make_golden.py beam_box [tw ...]     # D2Q37 1024^2 box, hours
   python tests/golden/make_golden.py batch_subsample       # seeded 4 of the 256-solve batch
   python tests/golden/make_golden.py wide_plate            # 64x2048 plates, tau*omega 0.01, 100
+  python tests/golden/make_golden.py wall_box              # 256^2 box, diffuse and specular faces
   options: --threads N
 
 The batch subsample runs each drawn solve for its full 20 480 steps, except
@@ -42,7 +43,9 @@ def oracle_params(s, threads):
         geometry={W.PLATE: O.GEOM_PLATE, W.BOX: O.GEOM_BOX, W.PERIODIC: O.GEOM_PERIODIC}[s.geometry],
         far=O.FAR_WALL if s.far == W.FAR_WALL else O.FAR_EQ,
         collision=O.COLL_REGULARIZED if s.collision == "regularized" else O.COLL_BGK,
-        box_x0=s.box[0], box_y0=s.box[1], box_lx=s.box[2], box_ly=s.box[3], nthreads=threads)
+        box_x0=s.box[0], box_y0=s.box[1], box_lx=s.box[2], box_ly=s.box[3], nthreads=threads,
+        wall={"bb": O.WALL_BB, "ds": O.WALL_DS, "maxwell": O.WALL_MAXWELL}[s.wall],
+        sigma=s.accommodation)
 
 
 def run_case(s, variant, threads, stride):
@@ -82,7 +85,7 @@ def write(name, obj):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("case", choices=["stokes_plate", "plate_sweep", "beam_box", "batch_subsample",
-                                     "wide_plate"])
+                                     "wide_plate", "wall_box"])
     ap.add_argument("tau_omega", nargs="*", type=float)
     ap.add_argument("--threads", type=int, default=0)
     a = ap.parse_args()
@@ -108,6 +111,11 @@ def main():
         for far in (W.FAR_WALL, W.FAR_EQ):
             for tw in a.tau_omega or (0.01, 100.0):
                 s = W.wide_plate(tw, far, storage="f64")
+                write(s.name, run_case(s, "f64", a.threads, 97))
+    elif a.case == "wall_box":
+        for tw in a.tau_omega or (1.0,):
+            for wall, sigma in (("ds", 1.0), ("maxwell", 0.0)):
+                s = W.wall_box(tw, wall, sigma, storage="f64")
                 write(s.name, run_case(s, "f64", a.threads, 97))
     else:
         for tw in a.tau_omega or W.BEAM_TAU_OMEGA:

@@ -114,8 +114,12 @@ def _box(**kw):
     (_box, {"representation": 4}, B.EINVAL),
     (_box, {"representation": B.REPR_COEFFICIENTS_NOLOAD, "collision": B.COLL_BGK}, B.EINVAL),
     (_box, {"representation": B.REPR_COEFFICIENTS, "collision": B.COLL_BGK}, B.EINVAL),
-    (_box, {"wall": B.WALL_DS}, B.EINVAL),
-    (_box, {"wall": B.WALL_MAXWELL, "accommodation": 0.5}, B.EINVAL),
+    (_box, {"wall": B.WALL_DS, "representation": B.REPR_COEFFICIENTS}, B.EINVAL),
+    (_box, {"wall": B.WALL_MAXWELL, "accommodation": 0.5,
+            "representation": B.REPR_COEFFICIENTS_NOLOAD}, B.EINVAL),
+    (_box, {"wall": B.WALL_DS, "box_x0": 3, "box_lx": 300, "box_y0": 3, "box_ly": 300,
+            "nx": 310, "ny": 310}, B.EINVAL),  # 1200 face columns
+    (_box, {"wall": B.WALL_MAXWELL, "accommodation": 1.5}, B.EINVAL),
     (_plate, {"wall": B.WALL_MAXWELL, "accommodation": -0.1}, B.EINVAL),
     (_plate, {"wall": B.WALL_MAXWELL, "accommodation": 1.5}, B.EINVAL),
     (_plate, {"wall": B.WALL_MAXWELL, "accommodation": float("nan")}, B.EINVAL),
@@ -155,6 +159,17 @@ def test_params_without_loads_pick_the_coefficient_buffer_only():
     assert P.params_from_solve(s).representation == B.REPR_AUTO
     narrow = W.plate_sweep(1.0, ny=64).scaled(100, 50)
     assert P.params_from_solve(narrow, loads=False).representation == B.REPR_AUTO
+
+
+def test_diffuse_and_maxwell_boxes_keep_populations():
+    """A box with diffuse or Maxwell faces is kept as populations: two
+    population buffers, more than the coefficient state of a bounce-back box
+    of the same size."""
+    cells = 128 * 128
+    for kw in ({"wall": B.WALL_DS}, {"wall": B.WALL_MAXWELL, "accommodation": 0.4}):
+        n = P.required_bytes(_box(**kw))
+        assert n >= 2 * 37 * cells * 4
+    assert P.required_bytes(_box()) < 2 * 37 * cells * 4
 
 
 def test_diffuse_and_maxwell_walls_on_a_plate_are_accepted():

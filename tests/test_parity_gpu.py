@@ -155,6 +155,40 @@ def test_small_parity_maxwell_wall(P, name, storage, repr_, sigma):
     _small_parity(P, name, storage, repr_, wall="maxwell", sigma=sigma)
 
 
+@pytest.mark.parametrize("wall,sigma", [("ds", 1.0), ("maxwell", 0.0), ("maxwell", 0.6)])
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("name", ["q9_box", "q37_box", "q37_box_bgk"])
+def test_small_parity_box_walls(P, name, storage, wall, sigma):
+    """Diffuse, specular and mixed faces on the box (faces cut into columns,
+    corner links bounce back; the box is kept as populations) against the
+    oracle: populations after 40 steps, every per-step force, the impedance."""
+    _small_parity(P, name, storage, 1, wall=wall, sigma=sigma)
+
+
+@pytest.mark.parametrize("wall,sigma", [("ds", 1.0), ("maxwell", 0.0), ("maxwell", 0.6)])
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("Q", [9, 37])
+def test_box_walls_free_molecular(P, Q, storage, wall, sigma):
+    """Free streaming past the convex box from rest: every population that
+    reaches it is at rest, so each step's force is the closed form the link
+    enumeration gives (the free-molecular limit, eq. free-molecular, for these
+    faces; the oracle is pinned to the same enumeration)."""
+    from tests.test_oracle_pins import _free_molecular_box_force
+    v, w, th = P.lattice(Q)
+    box, om, n = (12, 14, 10, 7), 2 * math.pi / 50, 60
+    s = W.Solve(Q=Q, geometry=W.BOX, far=W.FAR_EQ, nx=40, ny=40, tau=float("inf"), omega=om,
+                u0=1e-3, box=box, nsteps=n, window_first=10, window_count=n - 10,
+                storage=storage, collision="bgk", wall=wall, accommodation=sigma)
+    fx, fy, z, _ = _gpu(P, s)
+    U = 1e-3 * np.sin(om * (np.arange(n) + 0.5))
+    expect = np.array([_free_molecular_box_force(v, w, th, box, u, sigma, wall)[0] for u in U])
+    tol = 1e-13 if storage == "f64" else 2e-7
+    # the sums cancel O(1) rest-state terms: compare at that scale
+    scale = max(np.max(np.abs(expect)), 1.0) if storage == "f64" else np.max(np.abs(expect))
+    assert np.max(np.abs(fx - expect)) <= tol * scale
+    assert np.max(np.abs(fy)) <= tol * scale
+
+
 @pytest.mark.parametrize("tile", [1, 3])
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
 @pytest.mark.parametrize("name", ["q9_box", "q37_box", "q37_plate_eq_wide", "q37_periodic",
@@ -265,6 +299,102 @@ def test_beam_box_full(P, tw):
     assert abs(cmath.phase(z["Z"]) - cmath.phase(Zo)) <= 1e-4
     _cmp_samples(fx, g, 1e-3)
     assert np.max(np.abs(fy)) <= 1e-5 * np.max(np.abs(fx))
+
+
+def _solve_from_golden(g, storage="f32dev"):
+    """The workload a stored oracle run was made for, in the given storage."""
+    d = dict(g["solve"])
+    d["box"] = tuple(d["box"])
+    d["storage"] = storage
+    return W.Solve(**d)
+
+
+def _batch_full(P, names):
+    """Run the stored workloads `names` (FP32 deviation storage, the
+    representation the library picks, from rest) as one batch; return the
+    (golden, solve, force history, impedance) of each."""
+    import torch
+    gs = [_golden(n) for n in names]
+    solves = [_solve_from_golden(g) for g in gs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        svs = [P.Solver(P.params_from_solve(s, loads=False), stream=stream) for s in solves]
+        b = P.Batch(stream)
+        try:
+            for sv, s in zip(svs, solves):
+                print(f"case {s.name} {s.nx}x{s.ny} box {s.box} tau*omega {s.tau_omega:.4g} "
+                      f"steps {s.nsteps} repr {sv.representation}", flush=True)
+                b.add(sv)
+            b.step(max(s.nsteps for s in solves))
+            b.synchronize()
+            out = []
+            for g, s, sv in zip(gs, solves, svs):
+                fx, _ = sv.force_history(0, s.nsteps)
+                out.append((g, s, fx, sv.impedance(), sv.representation))
+        finally:
+            b.close()
+            for sv in svs:
+                sv.close()
+    return out
+
+
+def _assert_t2(z, g, name):
+    """T2: |Z| within 1e-4 relative and the phase within 1e-4 rad of the
+    stored FP64 oracle run."""
+    Zo = complex(g["fit"]["R"], g["fit"]["X"])
+    dz = abs(abs(z["Z"]) / abs(Zo) - 1)
+    dp = abs(cmath.phase(z["Z"]) - cmath.phase(Zo))
+    print(f"{name}: Z={z['Z']:.10g} oracle={Zo:.10g} |Z| {dz:.2e} phase {dp:.2e}", flush=True)
+    assert dz <= 1e-4 and dp <= 1e-4, (name, dz, dp)
+
+
+WIDE_PLATES = [f"wide_plate_{far}_tw{tw:g}" for far in ("wall", "eq") for tw in (0.01, 100.0)]
+
+
+def test_wide_plates_full_in_batch(P):
+    """64 x 2048 plates (kept as H2 coefficients, the coefficient kernel's
+    plate path) at tau*omega = 0.01 and 100 with the stationary far wall and
+    with the rest-equilibrium far field, 20 480 steps each, advanced as one
+    batch in FP32: impedance within T2 of the stored FP64 oracle runs, and
+    every stored force sample within 1e-3 of the force scale."""
+    for g, s, fx, z, repr_ in _batch_full(P, WIDE_PLATES):
+        assert repr_ == P.lbm.REPR_COEFFICIENTS
+        _assert_t2(z, g, s.name)
+        _cmp_samples(fx, g, 1e-3)
+
+
+WALL_BOXES = ["wall_box_ds_tw1", "wall_box_maxwell0_tw1"]
+
+
+def test_wall_boxes_full_in_batch(P):
+    """The 32 x 16 body in a 256^2 domain with diffuse and with specular
+    faces, tau*omega = 1, 20 480 steps, advanced as one batch in FP32:
+    impedance within T2 of the stored FP64 oracle runs, every stored force
+    sample within 1e-3 of the force scale, and no lift beyond rounding."""
+    for g, s, fx, z, repr_ in _batch_full(P, WALL_BOXES):
+        assert repr_ == P.lbm.REPR_POPULATIONS
+        _assert_t2(z, g, s.name)
+        _cmp_samples(fx, g, 1e-3)
+
+
+def _subsample_names():
+    small, large, drawn = W.batch_parity_subsample()
+    return [f"batch_{i}" for i in [small] + drawn + [large]]
+
+
+def test_batch_subsample_full(P):
+    """The seeded 4-solve subsample of the 256-solve batch (its smallest and
+    largest solve and two drawn by PCG64(40)), from rest, as one batch in FP32
+    with the representation the library picks: every solve for its full
+    20 480 steps except the largest (2026 x 2026), stored for 4096 steps;
+    impedance within T2 of the stored FP64 oracle runs."""
+    names = [n for n in _subsample_names()
+             if os.path.exists(os.path.join(GOLDEN, n + ".json"))]
+    if not names:
+        pytest.skip("no stored oracle run of the subsample")
+    for g, s, fx, z, repr_ in _batch_full(P, names):
+        _assert_t2(z, g, s.name)
+        _cmp_samples(fx, g, 1e-3)
 
 
 # ------------------------------------------------------------------ behaviour
