@@ -183,11 +183,11 @@ def cpu_baseline(solve, budget_s):
 
 
 def sweep_mode(a):
-    """Batched sweep vs the plain one-solve-at-a-time loop on a bounded sample
-    of the 256-solve batch workload: the first `--sweep-solves` solves of the
-    seeded draw, each run for `--sweep-steps` steps (lock-in over the second
-    half).  Prints solves/s and MLUPS of both and the largest relative
-    impedance difference between them."""
+    """Batched sweep vs the plain one-solve-at-a-time loop on the 256-solve
+    batch workload (or the first `--sweep-solves` solves of the seeded draw),
+    each run for `--sweep-steps` steps (lock-in over the second half; 20 480 =
+    10 periods of transient and 10 of window).  Prints solves/s and MLUPS of
+    both and the largest relative impedance difference between them."""
     import torch
     import lbm_inputs as W
     import paper_0904_4504_amd as P
@@ -207,12 +207,16 @@ def sweep_mode(a):
             sv.synchronize()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        solvers = [P.Solver(P.params_from_solve(s, tile=tile), stream=stream) for s in solves]
+        solvers = [P.Solver(P.params_from_solve(s, tile=tile, loads=False), stream=stream)
+                   for s in solves]
         batch = P.Batch(stream)
         for sv in solvers:
             batch.add(sv)
-        batch.step(a.sweep_steps)
-        batch.synchronize()
+        for done in range(0, a.sweep_steps, 2048):
+            batch.step(min(2048, a.sweep_steps - done))
+            batch.synchronize()
+            print(f"[batched] {min(done + 2048, a.sweep_steps)}/{a.sweep_steps} steps, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         zb = [sv.impedance() for sv in solvers]
         batch.close()
         for sv in solvers:
@@ -220,11 +224,14 @@ def sweep_mode(a):
         tb = time.perf_counter() - t0
         t0 = time.perf_counter()
         zp = []
-        for s in solves:
-            with P.Solver(P.params_from_solve(s, tile=tile), stream=stream) as sv:
+        for k, s in enumerate(solves):
+            with P.Solver(P.params_from_solve(s, tile=tile, loads=False), stream=stream) as sv:
                 sv.step(a.sweep_steps)
                 sv.synchronize()
                 zp.append(sv.impedance())
+            if (k + 1) % 16 == 0:
+                print(f"[plain] {k + 1}/{len(solves)} solves, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
         tp = time.perf_counter() - t0
     dz = max(abs(x["Z"] - y["Z"]) / abs(y["Z"]) for x, y in zip(zb, zp))
     out = {"metric": "sweep solves/s (batched vs plain loop)", "value": len(solves) / tb,
@@ -243,38 +250,48 @@ def sweep_mode(a):
 
 def serving_mode(a):
     """Continuous batching vs the plain loop on the serving mix (1 box : 4
-    plates), with drive periods of `--serve-period` steps (10 + 10 periods per
+    plates), drive period `--serve-period` steps (10 + 10 periods per
     request).  Capacity is measured with every request queued at t = 0; the
-    Poisson traces then run at 0.5, 0.8 and 0.95 of it through both paths."""
+    Poisson traces then run at 0.5, 0.8 and 0.95 of it through both paths.
+    Each trace has `--serve-warmup` + `--serve-requests` requests; latencies
+    and solves/s are taken over the requests after the warm-up ones."""
     import torch
     import lbm_inputs as W
     from paper_0904_4504_amd import serve as S
+    from paper_0904_4504_amd.serve import _summary
     torch.cuda.set_device(0)
-    n = a.serve_requests
-    burst = [(0.0, s) for _, s in W.serving_trace(1.0, n, period=a.serve_period)]
-    # warm-up
-    S.serve(burst[:4], chunk=a.serve_chunk)
-    _, cap = S.serve(burst, chunk=a.serve_chunk)
+    warm, n = a.serve_warmup, a.serve_requests
+    total = warm + n
+
+    def after_warmup(reqs, mode):
+        keep = reqs[warm:]
+        wall = max(r.done for r in keep) - keep[0].arrival
+        return _summary(keep, wall, mode)
+
+    burst = [(0.0, s) for _, s in W.serving_trace(1.0, total, period=a.serve_period)]
+    S.serve(burst[:4], chunk=a.serve_chunk)  # warm-up: code objects, graphs
+    _, cap = S.serve(burst, chunk=a.serve_chunk, progress="capacity")
     capacity = cap["solves_per_s"]
     rates = []
+    keys = ("solves_per_s", "latency_p50_s", "latency_p99_s", "wall_s")
     for f in (0.5, 0.8, 0.95):
-        trace = W.serving_trace(f * capacity, n, period=a.serve_period)
-        rb, sb = S.serve(trace, chunk=a.serve_chunk)
-        rp, sp = S.serve_plain(trace)
+        trace = W.serving_trace(f * capacity, total, period=a.serve_period)
+        rb, sb = S.serve(trace, chunk=a.serve_chunk, progress=f"batched {f}")
+        rp, _ = S.serve_plain(trace, progress=f"plain {f}")
         dz = max(abs(x.result["Z"] - y.result["Z"]) / abs(y.result["Z"]) for x, y in zip(rb, rp))
+        b, p = after_warmup(rb, "batched"), after_warmup(rp, "plain")
         rates.append({"load": f, "rate_per_s": f * capacity,
-                      "batched": {k: sb[k] for k in ("solves_per_s", "latency_p50_s",
-                                                     "latency_p99_s", "wall_s")},
-                      "plain": {k: sp[k] for k in ("solves_per_s", "latency_p50_s",
-                                                   "latency_p99_s", "wall_s")},
+                      "batched": dict({k: b[k] for k in keys}, host_fraction=sb["host_fraction"]),
+                      "plain": {k: p[k] for k in keys},
                       "max_rel_dZ_batched_vs_plain": dz})
     out = {"metric": "serving solves/s and p50/p99 latency (continuous batching vs plain loop)",
            "value": capacity, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
            "data": "synthetic", "rates": rates,
-           "config": {"workload": f"serving mix: {n} requests per rate, 1 box (1024x1024, body "
-                                  f"32x16) : 4 plates (4 x 1024..8192), tau*omega 1e-3..1e3, "
-                                  f"period {a.serve_period} steps, 10 + 10 periods per request, "
-                                  f"D2Q37 FP32, HBM budget 200 GB",
+           "capacity_host_fraction": cap["host_fraction"],
+           "config": {"workload": f"serving mix: {warm} warm-up + {n} requests per rate, 1 box "
+                                  f"(1024x1024, body 32x16) : 4 plates (4 x 1024..8192), "
+                                  f"tau*omega 1e-3..1e3, period {a.serve_period} steps, "
+                                  f"10 + 10 periods per request, D2Q37 FP32, HBM budget 200 GB",
                       "chunk_steps": a.serve_chunk}}
     print(json.dumps(out), flush=True)
 
@@ -292,11 +309,12 @@ def main():
     ap.add_argument("--tile", type=int, default=0,
                     help="kernel tile (cells per thread of the population or the coefficient "
                          "kernel); 0 = library default")
-    ap.add_argument("--sweep-solves", type=int, default=32)
-    ap.add_argument("--sweep-steps", type=int, default=2048)
-    ap.add_argument("--serve-requests", type=int, default=60)
-    ap.add_argument("--serve-period", type=int, default=128)
-    ap.add_argument("--serve-chunk", type=int, default=128)
+    ap.add_argument("--sweep-solves", type=int, default=256)
+    ap.add_argument("--sweep-steps", type=int, default=20480)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-warmup", type=int, default=40)
+    ap.add_argument("--serve-period", type=int, default=1024)
+    ap.add_argument("--serve-chunk", type=int, default=1024)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solves of a sweep are independent and would "

@@ -35,9 +35,9 @@ class Request:
         self.result = None
 
 
-def _summary(reqs, wall, mode):
+def _summary(reqs, wall, mode, host_s=None):
     lat = np.array([r.done - r.arrival for r in reqs])
-    return {
+    out = {
         "mode": mode,
         "requests": len(reqs),
         "wall_s": wall,
@@ -46,6 +46,18 @@ def _summary(reqs, wall, mode):
         "latency_p99_s": float(np.percentile(lat, 99)),
         "latency_mean_s": float(lat.mean()),
     }
+    if host_s is not None:
+        # time the loop spent on the host between device chunks (admission,
+        # solver creation, retirement, read-out), while the device idled
+        out["host_s"] = host_s
+        out["host_fraction"] = host_s / wall if wall > 0 else float("nan")
+    return out
+
+
+def _progress(tag, done, total, t0, clock):
+    if done % 20 == 0 or done == total:
+        print(f"[{tag}] {done}/{total} requests done, {clock() - t0:.1f} s", file=sys.stderr,
+              flush=True)
 
 
 def _finish(req):
@@ -55,9 +67,12 @@ def _finish(req):
 
 
 def serve(trace, budget_bytes=200e9, chunk=256, stream=None, clock=time.perf_counter,
-          max_resident=4096):
+          max_resident=4096, progress=None):
     """Continuous batching.  trace: [(arrival_s, lbm_inputs.Solve)] sorted by
-    arrival.  Returns (requests with results and timestamps, summary)."""
+    arrival.  Each device chunk runs `chunk` steps or up to the next
+    completion, whichever comes first, so a finished request is retired (and
+    its memory freed for the queue) at the step it ends.  Returns (requests
+    with results and timestamps, summary)."""
     import torch
     stream = stream or torch.cuda.Stream()
     pending = collections.deque(Request(i, t, s) for i, (t, s) in enumerate(trace))
@@ -67,12 +82,15 @@ def serve(trace, budget_bytes=200e9, chunk=256, stream=None, clock=time.perf_cou
     done = []
     batch = L.Batch(stream)
     t0 = clock()
+    host_s = 0.0
+    th = clock()
     try:
         while pending or waiting or resident:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
-                r.bytes = L.required_bytes(L.params_from_solve(r.solve)) + 512
+                # the solvers start from rest: no population-load buffer
+                r.bytes = L.required_bytes(L.params_from_solve(r.solve, loads=False)) + 512
                 if r.bytes > budget_bytes:
                     raise ValueError(f"request {r.rid} needs {r.bytes} B > budget")
                 waiting.append(r)
@@ -80,7 +98,7 @@ def serve(trace, budget_bytes=200e9, chunk=256, stream=None, clock=time.perf_cou
             while waiting and used + waiting[0].bytes <= budget_bytes and \
                     len(resident) < max_resident:
                 r = waiting.popleft()
-                r.solver = L.Solver(L.params_from_solve(r.solve), stream=stream)
+                r.solver = L.Solver(L.params_from_solve(r.solve, loads=False), stream=stream)
                 batch.add(r.solver)
                 r.admitted = clock() - t0
                 used += r.bytes
@@ -88,9 +106,13 @@ def serve(trace, budget_bytes=200e9, chunk=256, stream=None, clock=time.perf_cou
             if not resident:
                 if pending:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - (clock() - t0))))
+                th = clock()  # idle waiting for arrivals is not host work
                 continue
-            batch.step(chunk)
+            left = min(r.solve.nsteps - r.solver.steps_done for r in resident)
+            host_s += clock() - th
+            batch.step(min(chunk, left))
             batch.synchronize()
+            th = clock()
             still = []
             for r in resident:
                 if r.solver.steps_done >= r.solve.nsteps:
@@ -99,6 +121,8 @@ def serve(trace, budget_bytes=200e9, chunk=256, stream=None, clock=time.perf_cou
                     r.done = clock() - t0
                     used -= r.bytes
                     done.append(r)
+                    if progress:
+                        _progress(progress, len(done), len(trace), t0, clock)
                 else:
                     still.append(r)
             resident = still
@@ -109,10 +133,10 @@ def serve(trace, budget_bytes=200e9, chunk=256, stream=None, clock=time.perf_cou
                 r.solver.close()
         batch.close()
     done.sort(key=lambda r: r.rid)
-    return done, _summary(done, wall, "batched")
+    return done, _summary(done, wall, "batched", host_s)
 
 
-def serve_plain(trace, stream=None, clock=time.perf_counter):
+def serve_plain(trace, stream=None, clock=time.perf_counter, progress=None):
     """The plain loop: one request at a time, in arrival order, stepped alone."""
     import torch
     stream = stream or torch.cuda.Stream()
@@ -123,11 +147,13 @@ def serve_plain(trace, stream=None, clock=time.perf_counter):
         if r.arrival > now:
             time.sleep(r.arrival - now)
         r.admitted = clock() - t0
-        r.solver = L.Solver(L.params_from_solve(r.solve), stream=stream)
+        r.solver = L.Solver(L.params_from_solve(r.solve, loads=False), stream=stream)
         r.solver.step(r.solve.nsteps)
         r.solver.synchronize()
         _finish(r)
         r.done = clock() - t0
+        if progress:
+            _progress(progress, r.rid + 1, len(reqs), t0, clock)
     wall = clock() - t0
     return reqs, _summary(reqs, wall, "plain")
 

@@ -7,8 +7,9 @@ same quantity is R / (rho0 sqrt(theta/2) P), R the dissipative part of the
 impedance per unit span and P the wetted length of the section (the plate:
 one side of nx cells; a rectangle: its perimeter 2 (L_x + L_y)).
 
-`run_sweep` computes it for plates (AR = 0, bounce-back or diffuse wall) and
-rectangles (AR >= 1, bounce-back) over a tau*omega grid in one batched run.
+`run_sweep` computes it for plates (AR = 0) and rectangles (AR >= 1), each
+with bounce-back and with diffuse walls, over a tau*omega grid in one batched
+run.
 `quality_factor` turns a damping curve into the quality factor of a
 resonator immersed in nitrogen at pressure p (Sec. 6, the relation
 Q = Q_o / (1 + rho sqrt(theta/2) S/(m_o gamma_o) gamma_bar)), with
@@ -105,13 +106,14 @@ def sweep_solves(tau_omegas=TAU_OMEGA_GRID, period=1024, transient_periods=10,
             out.append((s, 0, wall, s.nx))
         for ar, lx in sorted(box_lx.items()):
             ly = ar * lx
-            s = W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=box_n, ny=box_n,
-                        tau=W.tau_lb(tw, omega), omega=omega, nsteps=steps,
-                        window_first=transient_periods * period,
-                        window_count=window_periods * period, tau_omega=tw,
-                        box=((box_n - lx) // 2, (box_n - ly) // 2, lx, ly),
-                        name=f"box_ar{ar}_tw{tw:g}")
-            out.append((s, ar, "bb", 2 * (lx + ly)))
+            for wall in ("bb", "ds"):
+                s = W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=box_n, ny=box_n,
+                            tau=W.tau_lb(tw, omega), omega=omega, nsteps=steps,
+                            window_first=transient_periods * period,
+                            window_count=window_periods * period, tau_omega=tw,
+                            box=((box_n - lx) // 2, (box_n - ly) // 2, lx, ly), wall=wall,
+                            name=f"box_ar{ar}_{wall}_tw{tw:g}")
+                out.append((s, ar, wall, 2 * (lx + ly)))
     return out
 
 
@@ -124,7 +126,8 @@ def run_sweep(points, stream=None):
     v, w, theta = L.lattice(37)
     recs = []
     with torch.cuda.stream(stream):
-        solvers = [L.Solver(L.params_from_solve(s), stream=stream) for s, _, _, _ in points]
+        solvers = [L.Solver(L.params_from_solve(s, loads=False), stream=stream)
+                   for s, _, _, _ in points]
         batch = L.Batch(stream)
         try:
             for sv in solvers:
@@ -145,7 +148,8 @@ def run_sweep(points, stream=None):
 
 def device_curves(recs, pressures_torr=(0.1, 1, 10, 100, 1000)):
     """Q/Q_o of each Table 1 device at the given pressures from the sweep
-    curve of its aspect ratio (diffuse wall where the sweep has one)."""
+    curve of its aspect ratio, with the diffuse wall (the model the paper
+    compares with experiment) and with bounce-back."""
     out = []
     for dev in TABLE1:
         curves = {}

@@ -159,6 +159,18 @@ def test_params_without_loads_pick_the_coefficient_buffer_only():
     assert P.params_from_solve(s).representation == B.REPR_AUTO
     narrow = W.plate_sweep(1.0, ny=64).scaled(100, 50)
     assert P.params_from_solve(narrow, loads=False).representation == B.REPR_AUTO
+    # boxes with diffuse or Maxwell faces stay populations
+    for wall in ("ds", "maxwell"):
+        walled = W.wall_box(1.0, wall, 0.5, n=128).scaled(100, 50)
+        p = P.params_from_solve(walled, loads=False)
+        assert p.representation == B.REPR_AUTO
+        P.required_bytes(p)
+    # every workload the sweep and the serving loop build is valid that way
+    from paper_0904_4504_amd import sweep as S
+    for s, _, _, _ in S.sweep_solves(period=64, plate_ny=64, box_n=160):
+        P.required_bytes(P.params_from_solve(s, loads=False))
+    for _, s in W.serving_trace(1.0, 20, period=64):
+        P.required_bytes(P.params_from_solve(s, loads=False))
 
 
 def test_diffuse_and_maxwell_boxes_keep_populations():

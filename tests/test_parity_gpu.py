@@ -377,6 +377,26 @@ def test_wall_boxes_full_in_batch(P):
         _cmp_samples(fx, g, 1e-3)
 
 
+def test_sweep_matches_oracle_on_reduced_points(P):
+    """The damping sweep (plates AR = 0, rectangles AR = 1, 10, 26; bounce-back
+    and diffuse walls) run by `run_sweep` as one batch on reduced points
+    (period 64, 2 + 2 periods, plates 4 x 96, rectangles 8 x 8, 4 x 40, 3 x 78
+    in 128^2) at tau*omega 0.01 and 1: every impedance within T2 of the
+    oracle, and the nondimensional damping is R / (rho0 sqrt(theta/2) P)."""
+    from paper_0904_4504_amd import sweep as S
+    pts = S.sweep_solves(tau_omegas=(0.01, 1.0), period=64, transient_periods=2,
+                         window_periods=2, plate_ny=96, box_n=128,
+                         box_lx={1: 8, 10: 4, 26: 3})
+    recs = S.run_sweep(pts)
+    v, w, th = P.lattice(37)
+    for (s, ar, wall, perim), r in zip(pts, recs):
+        fx, _, _ = O.run(_oracle_params(s), s.nsteps)
+        zo = O.lockin_fit(fx, s.window_first, s.window_count, s.omega, s.u0)
+        _assert_t2({"Z": complex(r["R"], r["X"])}, {"fit": zo}, s.name)
+        assert r["gamma_bar"] == pytest.approx(r["R"] / (s.rho0 * math.sqrt(th / 2) * perim),
+                                               rel=1e-15)
+
+
 def _subsample_names():
     small, large, drawn = W.batch_parity_subsample()
     return [f"batch_{i}" for i in [small] + drawn + [large]]
@@ -737,6 +757,34 @@ def test_batch_rejects_mismatched_members(P):
 
 # ------------------------------------------------------------------ serving
 
+def test_served_impedances_match_oracle(P):
+    """Requests of the serving loop (boxes and plates arriving over time,
+    budget-limited admission) against the oracle: every served impedance
+    within T2 of the FP64 oracle run of the same solve from rest."""
+    import torch
+    from paper_0904_4504_amd import serve
+    om = 2 * math.pi / 64
+    trace = []
+    for k in range(5):
+        if k % 2 == 0:
+            s = W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=96, ny=72 + 8 * k, tau=0.8 + k,
+                        omega=om, box=(40, 30, 14, 9), nsteps=256, window_first=128,
+                        window_count=128, name=f"box{k}")
+        else:
+            s = W.Solve(Q=37, geometry=W.PLATE, far=W.FAR_WALL, nx=4, ny=300 + 50 * k,
+                        tau=0.6 + 5.0 * k, omega=om, nsteps=320, window_first=128,
+                        window_count=192, name=f"plate{k}")
+        trace.append((0.003 * k, s))
+    need = sorted(P.required_bytes(P.params_from_solve(s, loads=False)) for _, s in trace)
+    reqs, _ = serve.serve(trace, budget_bytes=need[-1] + need[-2] + 2048, chunk=64,
+                          stream=torch.cuda.Stream())
+    for r in reqs:
+        s = r.solve
+        fx, _, _ = O.run(_oracle_params(s), s.nsteps)
+        zo = O.lockin_fit(fx, s.window_first, s.window_count, s.omega, s.u0)
+        _assert_t2(r.result, {"fit": zo}, s.name)
+
+
 def test_serving_results_same_alone_and_in_mix(P):
     """Requests arriving while others run are admitted as memory frees up (a
     budget of about two requests forces queueing), advance together in the
@@ -756,7 +804,7 @@ def test_serving_results_same_alone_and_in_mix(P):
                         window_count=192 + 64 * k, name=f"plate{k}")
         trace.append((0.005 * k, s))
     stream = torch.cuda.Stream()
-    need = sorted(P.required_bytes(P.params_from_solve(s)) for _, s in trace)
+    need = sorted(P.required_bytes(P.params_from_solve(s, loads=False)) for _, s in trace)
     reqs, summ = serve.serve(trace, budget_bytes=need[-1] + need[-2] + 2048, chunk=48,
                              stream=stream)
     assert summ["requests"] == 7

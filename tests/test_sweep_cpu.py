@@ -1,6 +1,7 @@
 """Damping sweep post-processing (no GPU): the nondimensional damping, the
 quality factor of a Table 1 resonator, and the Newtonian cylinder comparator
 (Sec. 3, eq. hydro_function) against the oracle's stored beam-box results."""
+import cmath
 import json
 import math
 import os
@@ -8,6 +9,8 @@ import os
 import numpy as np
 import pytest
 
+import lbm_inputs as W
+import oracle as O
 from paper_0904_4504_amd import sweep as S
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -83,11 +86,38 @@ def test_box_against_newtonian_cylinder(tw):
 def test_sweep_points_cover_the_grid():
     pts = S.sweep_solves(period=64, plate_ny=64, box_n=160)
     combos = {(ar, wall) for _, ar, wall, _ in pts}
-    assert combos == {(0, "bb"), (0, "ds"), (1, "bb"), (10, "bb"), (26, "bb")}
+    assert combos == {(ar, wall) for ar in (0, 1, 10, 26) for wall in ("bb", "ds")}
     assert sorted({s.tau_omega for s, _, _, _ in pts}) == list(S.TAU_OMEGA_GRID)
     for s, ar, wall, perim in pts:
+        assert s.wall == wall
         if ar:
             assert s.box[3] == ar * s.box[2] and perim == 2 * (s.box[2] + s.box[3])
-            assert s.wall == "bb"
         else:
             assert perim == s.nx
+
+
+def test_plate_sweep_against_the_h2_telegraph_law():
+    """P9, reported rather than gated at the stored precision: the
+    regularized scheme keeps f in H2, so its third moment closes as
+    Q_xyy = rho theta u_x and the shear wave obeys a telegraph law,
+    tau u_tt + u_t = nu u_yy; in a channel of height H with the plate at one
+    side Z/(rho0 sqrt(theta)) = sqrt(i tw/(1 + i tw)) coth(kH),
+    k = (omega/sqrt(theta)) sqrt(i (1 + i tw)/tw).  Against the stored oracle
+    runs of the 4 x 2048 plate (impedance per unit length): |Z| within 1e-3
+    and the phase within 5e-3 rad for tau*omega <= 1; at 10 and 100 the
+    channel resonance makes the closure's Knudsen-layer error visible (about
+    1 % and 20 %), so those are only printed."""
+    v, w, th = O.lattice(37, "ld")
+    for tw in W.PLATE_SWEEP_TAU_OMEGA:
+        with open(os.path.join(GOLDEN, f"plate_sweep_tw{tw:g}.json")) as fh:
+            g = json.load(fh)
+        s = g["solve"]
+        Zo = complex(g["fit"]["R"], g["fit"]["X"]) / s["nx"]
+        k = (s["omega"] / math.sqrt(th)) * cmath.sqrt(1j * (1 + 1j * tw) / tw)
+        Zt = math.sqrt(th) * cmath.sqrt(1j * tw / (1 + 1j * tw)) / cmath.tanh(k * s["ny"])
+        dz = abs(Zo) / abs(Zt) - 1
+        dp = cmath.phase(Zo) - cmath.phase(Zt)
+        print(f"tau*omega {tw:g}: oracle {Zo:.6f}, telegraph {Zt:.6f}, |Z| {dz:+.2e}, "
+              f"phase {dp:+.2e} rad")
+        if tw <= 1:
+            assert abs(dz) <= 1e-3 and abs(dp) <= 5e-3
