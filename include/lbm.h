@@ -220,19 +220,28 @@ int lbm_representation(const lbm_solver* s, int* repr);
 /* Steps enqueued so far (host-side count; no wait). */
 int lbm_steps_done(const lbm_solver* s, int64_t* n);
 
-/* Copy F_x[n], F_y[n] for n in [first, first + count) into caller arrays
+/* Force of the gas on the moving wall or body at step n, the F_f of Sec. 2
+ * computed by momentum exchange across the wall links (Sec. 6; eq. BB, and
+ * eq. DS for the diffuse wall), FP64, stamped at t_n = n + 1/2.
+ * Copy F_x[n], F_y[n] for n in [first, first + count) into caller arrays
  * (either may be NULL).  Waits for the stream.  LBM_ERANGE unless the
  * samples were computed and are still in the ring.  On an unstable solver
  * the arrays are filled and LBM_EUNSTABLE is returned (also by lbm_lockin
  * and lbm_impedance). */
 int lbm_force_history(lbm_solver* s, int64_t first, int64_t count, double* fx, double* fy);
 
-/* Lock-in sums over the part of the window computed so far (waits):
+/* Lock-in sums of the force against the drive's phase (Sec. 2: the part of
+ * F_f in phase with the velocity gives the damping, the part in phase with
+ * the acceleration the added mass), over the part of the window computed so
+ * far (waits):
  * sums = {sum F_x sin(omega t_n), sum F_x cos(omega t_n), sum F_x,
  *         the same three for F_y};  *nsamples = steps summed. */
 int lbm_lockin(lbm_solver* s, double sums[6], int64_t* nsamples);
 
-/* Least-squares fit F_x[n] ~ a sin(omega t_n) + b cos(omega t_n) + c over
+/* Impedance of the oscillating wall or body, the complex Z = R + iX of
+ * eq. nems_W_tw, from the decomposition F_f = -m(gamma x_t + beta x_tt) of
+ * Sec. 2 (R the damping, X / omega the added mass).
+ * Least-squares fit F_x[n] ~ a sin(omega t_n) + b cos(omega t_n) + c over
  * the computed part of the window (3x3 normal equations, long double), and
  * the impedance of the drive u = u0 sin(omega t): R = -a/u0, X = -b/u0.
  * out = {a, b, c, R, X}.  Waits.  LBM_ERANGE if fewer than 3 samples. */
