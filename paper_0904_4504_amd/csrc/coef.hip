@@ -450,7 +450,7 @@ template <class L, typename S, int RB, bool DSW>
 __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S>& t, int tile,
                                              const Pair<S>* C, const KernelLattice& lat,
                                              const CoefConst<S>& cc, int tid,
-                                             S (&res)[RB][6], double U) {
+                                             S (&res)[RB][6], uint32_t& valid, double U) {
   using T = CoefTile<L, RB>;
   constexpr int R = T::R, HW = T::HW;
   const int nx = d.nx, ny = d.ny;
@@ -567,15 +567,21 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S
   const S h2 = cc.half_inv_theta2;
   const S om = (S)d.inv_tau;
   const S rho0 = (S)d.rho0;
+  // Every lane runs the collision of all its rows: cells outside the lattice
+  // or inside the body see only staged zeros and finite sums, and their
+  // results are dropped by the store (bit k of `valid`), so no lane leaves
+  // the straight-line code.
+  bool bad = false;
   // (a compile-time loop: unrolled whatever the size of the wall code)
   static_for<0, RB>([&](auto kc) __attribute__((always_inline)) {
     constexpr int k = decltype(kc)::value;
     Mom<S> m = acc[k];
     const int y = yb + k;
-    if (y >= ny || x >= nx) return;
-    if (is_box && y >= by0 && y < by1 && x >= bx0 && x < bx1) return;  // solid
+    const bool in = y < ny && x < nx && !(is_box && y >= by0 && y < by1 && x >= bx0 && x < bx1);
+    valid |= in ? 1u << k : 0u;
     if (wave_has_wall) {
-      const bool near = (y >= wy0 && y < wy1 && x >= wx0 && x < wx1) || (far_band && y >= ny - R);
+      const bool near =
+          in && ((y >= wy0 && y < wy1 && x >= wx0 && x < wx1) || (far_band && y >= ny - R));
       if (near) {
         S ladd = (S)(d.ladd_scale * U);
         // computed per cell in the band: keeps its products out of the common path
@@ -590,7 +596,7 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S
       inv_rho = __builtin_amdgcn_rcpf(rho);  // 1 ulp; the FP32 form's error is dominated by storage
     else
       inv_rho = S(1) / rho;
-    if (!(rho > S(0) && rho < S(INFINITY))) d.state->unstable = 1;
+    bad |= in && !(rho > S(0) && rho < S(INFINITY));
     const S uxx = jx * jx * inv_rho, uxy = jx * jy * inv_rho, uyy = jy * jy * inv_rho;
     const S axx = m.v[3] - drho * th, ayy = m.v[5] - drho * th, axy = m.v[4];
     const S bxx = axx - om * (axx - uxx);
@@ -603,29 +609,27 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S
     res[k][4] = bxy * cc.inv_theta2;
     res[k][5] = byy * h2;
   });
+  if (bad) d.state->unstable = 1;
 }
 
 // Store the new coefficients of this thread's cells (those in the lattice
-// and the fluid).
+// and the fluid: bit k of `valid` for row k).
 template <class L, typename S, int RB>
 __device__ __forceinline__ void store_tile(const SolveDesc& d, const TileCtx<S>& t, int tile,
-                                           int tid, const S (&res)[RB][6]) {
+                                           int tid, const S (&res)[RB][6], uint32_t valid) {
   using T = CoefTile<L, RB>;
   const gptr<S> mout = as_global(t.mout);
-  const int nx = d.nx, ny = d.ny;
   const int64_t ks = d.mks;
   const int ys = (int)d.mys;
   gptr<S> pout[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) pout[k] = scalar_ptr(mout + k * ks);
-  const bool is_box = d.geom == GEOM_BOX;
   const int x = (tile % d.tiles_x) * kCoefTileW + (tid & 63);
   const int yb = (tile / d.tiles_x) * T::TH + (tid >> 6) * RB;
 #pragma unroll
   for (int k = 0; k < RB; ++k) {
+    if (!(valid & (1u << k))) continue;
     const int y = yb + k;
-    if (y >= ny || x >= nx) continue;
-    if (is_box && y >= d.by0 && y < d.by1 && x >= d.bx0 && x < d.bx1) continue;  // solid
     const uint32_t o = (uint32_t)(y * ys + x) * (uint32_t)sizeof(S);
     // plain (cached) stores: the next step reads these planes back, and a
     // state of 48 B per cell stays in the last-level cache between steps
@@ -689,8 +693,9 @@ __global__ __launch_bounds__(64 * kCoefWaves) void coef_kernel(const SolveDesc* 
   }
   __syncthreads();
   S res[RB][6];
-  compute_tile<L, S, RB, DSW>(d, ctx, wi.tile, C, lat, cc, tid, res, U);
-  store_tile<L, S, RB>(d, ctx, wi.tile, tid, res);
+  uint32_t valid = 0;
+  compute_tile<L, S, RB, DSW>(d, ctx, wi.tile, C, lat, cc, tid, res, valid, U);
+  store_tile<L, S, RB>(d, ctx, wi.tile, tid, res, valid);
 }
 
 template <class L, typename S, int RB>
