@@ -88,9 +88,9 @@ enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
  * includes the mass the moving face displaces); the specular image is the
  * population that left the source point mirrored through the face plane with
  * its normal velocity reversed, plus the moving-wall term on the faces normal
- * to the motion.  A box with diffuse or Maxwell faces is kept as populations
- * and has at most 1024 face columns (2 (box_lx + box_ly)).  The stationary
- * far wall of a plate stays bounce-back. */
+ * to the motion.  A box with diffuse or Maxwell faces has at most 1024 face
+ * columns (2 (box_lx + box_ly)).  The stationary far wall of a plate stays
+ * bounce-back. */
 enum { LBM_WALL_BB = 0, LBM_WALL_DS = 1, LBM_WALL_MAXWELL = 2 };
 
 /* Geometry.

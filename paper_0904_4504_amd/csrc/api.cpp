@@ -136,10 +136,8 @@ bool uses_coefficients(const lbm_params* p) {
   if (p->representation == LBM_REPR_COEFFICIENTS ||
       p->representation == LBM_REPR_COEFFICIENTS_NOLOAD)
     return true;
-  // a box with diffuse or Maxwell faces is kept as populations
   return p->representation == LBM_REPR_AUTO && p->collision == LBM_COLL_REGULARIZED &&
-         p->nx >= kCoefTileW && coefficient_plane_fits(p) &&
-         !(p->geometry == LBM_GEOM_BOX && p->wall != LBM_WALL_BB);
+         p->nx >= kCoefTileW && coefficient_plane_fits(p);
 }
 
 int validate(const lbm_params* p, HostLattice* lat) {
@@ -158,10 +156,9 @@ int validate(const lbm_params* p, HostLattice* lat) {
   const bool coef_asked = p->representation == LBM_REPR_COEFFICIENTS ||
                           p->representation == LBM_REPR_COEFFICIENTS_NOLOAD;
   if (coef_asked && p->collision != LBM_COLL_REGULARIZED) return LBM_EINVAL;
-  // a box with diffuse or Maxwell faces: populations only, at most
-  // kMaxWallCols face columns
+  // a box with diffuse or Maxwell faces: at most kMaxWallCols face columns
   if (p->wall != LBM_WALL_BB && p->geometry == LBM_GEOM_BOX &&
-      (coef_asked || 2 * ((int64_t)p->box_lx + p->box_ly) > kMaxWallCols))
+      2 * ((int64_t)p->box_lx + p->box_ly) > kMaxWallCols)
     return LBM_EINVAL;
   const int R = lat->R;
   if (p->nx < std::max(3, R) || p->ny < std::max(3, R)) return LBM_EINVAL;
@@ -277,6 +274,8 @@ void build_wall_tables(const lbm_params* p, const HostLattice& L, const Layout& 
     return -1;
   };
   long double sx = 0, sy = 0;
+  // crossing-mass weights of the current column over its cells' coefficients
+  long double mc[3][6];
   // the links of a fluid cell, in direction order
   auto add_cell = [&](int x, int y, int col) {
     for (int q = 0; q < L.Q; ++q) {
@@ -288,16 +287,29 @@ void build_wall_tables(const lbm_params* p, const HostLattice& L, const Layout& 
       const long double w = L.lw.w_orbit_ld[L.orbit[q]];
       WallLink l{};
       l.off_partner = L.opp[q] * lay.qs + py * lay.ys + px;
+      l.cell_partner = (int64_t)py * lay.mpitch + px;
       l.col = col;
       l.w = (double)w;
       l.vx = vx;
       l.vy = vy;
       const int face = face_of(x, y);
       l.normal = face >= 2;
-      if (face == 0 || face == 1)
+      if (face == 0 || face == 1) {
         l.off_spec = find(vx, -vy) * lay.qs + py * lay.ys + sxs;
-      else if (face >= 2)
+        l.cell_spec = (int64_t)py * lay.mpitch + sxs;
+      } else if (face >= 2) {
         l.off_spec = find(-vx, vy) * lay.qs + sys * lay.ys + px;
+        l.cell_spec = (int64_t)sys * lay.mpitch + px;
+      }
+      if (col >= 0) {
+        // the partner's distance from the face (it lies in the link's column)
+        const int k = face == 0 ? y0 - py : face == 1 ? py - (y1 - 1) : face == 2 ? x0 - px
+                                                                                  : px - (x1 - 1);
+        const long double g[6] = {1, -(long double)vx, -(long double)vy,
+                                  (long double)vx * vx, (long double)vx * vy,
+                                  (long double)vy * vy};
+        for (int j = 0; j < 6; ++j) mc[k - 1][j] += w * g[j];
+      }
       sx -= 2.0L * w * p->rho0 * vx;
       sy -= 2.0L * w * p->rho0 * vy;
       t->wlinks.push_back(l);
@@ -314,11 +326,16 @@ void build_wall_tables(const lbm_params* p, const HostLattice& L, const Layout& 
     else { face = 3; at = y0 + c - 2 * p->box_lx - p->box_ly; }
     WallCol& wc = t->wcols[(size_t)c];
     wc.first = (int32_t)t->wlinks.size();
+    for (auto& row : mc)
+      for (auto& v : row) v = 0;
     for (int k = 1; k <= R; ++k) {
       const int x = face <= 1 ? at : (face == 2 ? x0 - k : x1 - 1 + k);
       const int y = face >= 2 ? at : (face == 0 ? y0 - k : y1 - 1 + k);
+      wc.cell[k - 1] = (int64_t)y * lay.mpitch + x;
       add_cell(x, y, c);
     }
+    for (int k = 0; k < 3; ++k)
+      for (int j = 0; j < 6; ++j) wc.mc[k][j] = (double)mc[k][j];
     wc.count = (int32_t)t->wlinks.size() - wc.first;
     long double mr = 0, z1 = 0, z2 = 0, l1 = 0;
     for (int i = wc.first; i < wc.first + wc.count; ++i) {

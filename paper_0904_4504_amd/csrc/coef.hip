@@ -184,6 +184,24 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, const 
   // the coefficients of rows 0 .. R-1 (population q at row r crosses when
   // r < -v_qy)
   double cm = 0.0;
+  // box with diffuse or Maxwell faces: the face and column of this arrival
+  // cell; the column's crossing mass is linear in the coefficients of its R
+  // cells (weights from the host), each within R - 1 cells of this one
+  int face = -1, col = 0;
+  if (DSW && d.wall == WALL_DS && is_box) {
+    face = box_face<L::R>(d, x, y);
+    if (face >= 0) {
+      col = box_column(d, face, x, y);
+      const WallCol& wc = d.wcols[col];
+      static_for<0, L::R>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;  // the cell k + 1 cells from the face
+        const int cx = face == 2 ? d.bx0 - 1 - k : (face == 3 ? d.bx1 + k : x);
+        const int cy = face == 0 ? d.by0 - 1 - k : (face == 1 ? d.by1 + k : y);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) cm += wc.mc[k][j] * (double)coef(cx, cy, j);
+      });
+    }
+  }
   if (DSW && d.wall == WALL_DS && d.geom == GEOM_PLATE && y < L::R) {
     static_for<0, L::R>([&](auto rc) __attribute__((always_inline)) {
       constexpr int r = decltype(rc)::value;
@@ -209,6 +227,7 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, const 
         px = x < d.bx0 ? 2 * d.bx0 - 1 - sx : (x >= d.bx1 ? 2 * d.bx1 - 1 - sx : x);
         py = y < d.by0 ? 2 * d.by0 - 1 - sy : (y >= d.by1 ? 2 * d.by1 - 1 - sy : y);
         moving = true;
+        diffuse = DSW && face >= 0;  // corner links keep bounce-back
       }
     } else if (d.geom == GEOM_PLATE) {
       if constexpr (vy > 0) {
@@ -231,19 +250,37 @@ __device__ __forceinline__ Mom<S> add_links(Mom<S> m, const SolveDesc& d, const 
       const S wq = cc.w[o];
       S f;
       if (DSW && diffuse) {
-        double e = ds_arrival<vx>(d, U, cm, lat.w[L::orbit[q]], lat.theta);
+        const double wd = lat.w[L::orbit[q]];
+        double e = is_box ? ds_box_arrival(d.wcols[col], d.rho0, U, cm, wd, double(vx), lat.theta)
+                          : ds_arrival<vx>(d, U, cm, wd, lat.theta);
         if (d.sigma != 1.0) {
-          // specular share: the population of (vx, -vy) that crossed the
-          // wall from column x - vx at the mirror row (the staged halo holds
-          // the periodic image of a wrapped column)
-          const int sxw = x - vx;
-          double p = coef(sxw, py, 0);
-          if constexpr (vx != 0)
-            p += double(vx) * coef(sxw, py, 1) + double(vx * vx) * coef(sxw, py, 3);
-          if constexpr (vy != 0)
-            p += double(-vy) * coef(sxw, py, 2) + double(vy * vy) * coef(sxw, py, 5);
-          if constexpr (vx * vy != 0) p += double(-vx * vy) * coef(sxw, py, 4);
-          e = d.sigma * e + (1.0 - d.sigma) * lat.w[L::orbit[q]] * p;
+          double p;
+          if (!is_box || face <= 1) {
+            // specular share: the population of (vx, -vy) that crossed the
+            // wall or face from column x - vx at the mirror row (the staged
+            // halo holds the periodic image of a wrapped column)
+            const int sxw = x - vx;
+            p = coef(sxw, py, 0);
+            if constexpr (vx != 0)
+              p += double(vx) * coef(sxw, py, 1) + double(vx * vx) * coef(sxw, py, 3);
+            if constexpr (vy != 0)
+              p += double(-vy) * coef(sxw, py, 2) + double(vy * vy) * coef(sxw, py, 5);
+            if constexpr (vx * vy != 0) p += double(-vx * vy) * coef(sxw, py, 4);
+            p *= wd;
+          } else {
+            // a face normal to the motion: the population of (-vx, vy) that
+            // crossed it from row y - vy at the mirror column, plus the
+            // moving-wall term of the face moving along its normal
+            const int syw = y - vy;
+            p = coef(px, syw, 0);
+            if constexpr (vx != 0)
+              p += double(-vx) * coef(px, syw, 1) + double(vx * vx) * coef(px, syw, 3);
+            if constexpr (vy != 0)
+              p += double(vy) * coef(px, syw, 2) + double(vy * vy) * coef(px, syw, 5);
+            if constexpr (vx * vy != 0) p += double(-vx * vy) * coef(px, syw, 4);
+            p = wd * p + wd * double(vx) * d.ladd_scale * U;
+          }
+          e = d.sigma * e + (1.0 - d.sigma) * p;
         }
         f = (S)e;
       } else {

@@ -507,6 +507,45 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
       fx -= l.vx * (fp + a);
       fy -= l.vy * (fp + a);
     }
+  } else if (coeffs && d.nwlinks > 0) {
+    // the same two passes on the H2 coefficients of the input state: a
+    // population of velocity v at cell o is w_v (a0 + vx bx + vy by + vx^2 cxx
+    // + vx vy cxy + vy^2 cyy)(o)
+    const S* __restrict__ c = static_cast<const S*>(d.mbuf[n & 1]);
+    const int64_t ks = d.mks;
+    auto pop = [&](int64_t o, double w, double vx, double vy) {
+      return w * ((double)c[o] + vx * (double)c[ks + o] + vy * (double)c[2 * ks + o] +
+                  vx * vx * (double)c[3 * ks + o] + vx * vy * (double)c[4 * ks + o] +
+                  vy * vy * (double)c[5 * ks + o]);
+    };
+    __shared__ double cmass[kMaxWallCols];
+    for (int k = threadIdx.x; k < d.nwcols; k += kBlock) {
+      const WallCol& col = d.wcols[k];
+      double m = 0.0;
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 6; ++j) m += col.mc[r][j] * (double)c[j * ks + col.cell[r]];
+      cmass[k] = m;
+    }
+    __syncthreads();
+    const double U = d.drive[n].u;
+    const double ladd = d.ladd_scale * U;
+    for (int i = threadIdx.x; i < d.nwlinks; i += kBlock) {
+      const WallLink l = d.wlinks[i];
+      const double fp = pop(l.cell_partner, l.w, -l.vx, -l.vy);
+      double a;
+      if (l.col < 0) {
+        a = fp + l.w * l.vx * ladd;
+      } else {
+        a = ds_box_arrival(d.wcols[l.col], d.rho0, U, cmass[l.col], l.w, l.vx, d.theta);
+        if (d.sigma != 1.0) {
+          const double sp = l.normal ? pop(l.cell_spec, l.w, -l.vx, l.vy) + l.w * l.vx * ladd
+                                     : pop(l.cell_spec, l.w, l.vx, -l.vy);
+          a = d.sigma * a + (1.0 - d.sigma) * sp;
+        }
+      }
+      fx -= l.vx * (fp + a);
+      fy -= l.vy * (fp + a);
+    }
   } else if (coeffs) {
     const S* __restrict__ c = static_cast<const S*>(d.mbuf[n & 1]);
     const int64_t ks = d.mks;

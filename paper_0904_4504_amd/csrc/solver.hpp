@@ -66,19 +66,27 @@ struct ForceCell {
 // 1 / 2 theta) (the mass emitted per unit wall density is Mr + Z1 U + Z2 U^2),
 // L1 = sum 2 w_l vx_l / theta (the moving-wall terms bounce-back would add,
 // per unit rho0 U); the column's links are [first, first + count) of the link
-// table.
+// table.  For a solve kept as H2 coefficients: cell[k] is the coefficient
+// offset (y pitch + x) of the column's cell k + 1 cells from the face, and
+// the column's crossing mass is sum_k sum_j mc[k][j] c_j(cell[k]) (every
+// partner population df_{-v}(x_p) = w (a0 - vx bx - vy by + vx^2 cxx +
+// vx vy cxy + vy^2 cyy) is linear in the coefficients of its cell).
 struct WallCol {
   double Mr, Z1, Z2, L1;
   int32_t first, count;
+  int64_t cell[3];
+  double mc[3][6];
 };
 // One link of such a box: its bounce-back partner (the opposite population at
 // the mirror cell) and, on a face, its specular source (the population of
 // the velocity mirrored in the face's normal, at the source point mirrored
-// through the face plane), as element offsets into a population buffer; its
-// column (-1: a corner link, which keeps bounce-back); normal: the face is
-// normal to the motion (x faces); the arrival direction's weight and velocity.
+// through the face plane), as element offsets into a population buffer
+// (off_*) and as the cells' coefficient offsets (cell_*); its column (-1: a
+// corner link, which keeps bounce-back); normal: the face is normal to the
+// motion (x faces); the arrival direction's weight and velocity.
 struct WallLink {
   int64_t off_partner, off_spec;
+  int64_t cell_partner, cell_spec;
   int32_t col, normal;
   double w, vx, vy;
 };

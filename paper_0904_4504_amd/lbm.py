@@ -136,12 +136,10 @@ def default_params():
 
 def keeps_coefficients(s):
     """True if the automatic representation keeps this solve as H2
-    coefficients: regularized collision, nx >= 64, one coefficient plane
-    (ny x nx rounded up to 64) below 2 GiB, and not a box with diffuse or
-    Maxwell faces -- the library's rule."""
+    coefficients: regularized collision, nx >= 64 and one coefficient plane
+    (ny x nx rounded up to 64) below 2 GiB -- the library's rule."""
     es = 8 if s.storage == "f64" else 4
-    walled_box = s.geometry == "box" and getattr(s, "wall", "bb") != "bb"
-    return (s.collision == "regularized" and s.nx >= 64 and not walled_box
+    return (s.collision == "regularized" and s.nx >= 64
             and s.ny * ((s.nx + 63) // 64 * 64) * es < 2 ** 31)
 
 

@@ -114,9 +114,8 @@ def _box(**kw):
     (_box, {"representation": 4}, B.EINVAL),
     (_box, {"representation": B.REPR_COEFFICIENTS_NOLOAD, "collision": B.COLL_BGK}, B.EINVAL),
     (_box, {"representation": B.REPR_COEFFICIENTS, "collision": B.COLL_BGK}, B.EINVAL),
-    (_box, {"wall": B.WALL_DS, "representation": B.REPR_COEFFICIENTS}, B.EINVAL),
-    (_box, {"wall": B.WALL_MAXWELL, "accommodation": 0.5,
-            "representation": B.REPR_COEFFICIENTS_NOLOAD}, B.EINVAL),
+    (_box, {"wall": B.WALL_DS, "representation": B.REPR_COEFFICIENTS,
+            "collision": B.COLL_BGK}, B.EINVAL),
     (_box, {"wall": B.WALL_DS, "box_x0": 3, "box_lx": 300, "box_y0": 3, "box_ly": 300,
             "nx": 310, "ny": 310}, B.EINVAL),  # 1200 face columns
     (_box, {"wall": B.WALL_MAXWELL, "accommodation": 1.5}, B.EINVAL),
@@ -159,11 +158,11 @@ def test_params_without_loads_pick_the_coefficient_buffer_only():
     assert P.params_from_solve(s).representation == B.REPR_AUTO
     narrow = W.plate_sweep(1.0, ny=64).scaled(100, 50)
     assert P.params_from_solve(narrow, loads=False).representation == B.REPR_AUTO
-    # boxes with diffuse or Maxwell faces stay populations
+    # boxes with diffuse or Maxwell faces too
     for wall in ("ds", "maxwell"):
         walled = W.wall_box(1.0, wall, 0.5, n=128).scaled(100, 50)
         p = P.params_from_solve(walled, loads=False)
-        assert p.representation == B.REPR_AUTO
+        assert p.representation == B.REPR_COEFFICIENTS_NOLOAD
         P.required_bytes(p)
     # every workload the sweep and the serving loop build is valid that way
     from paper_0904_4504_amd import sweep as S
@@ -173,15 +172,19 @@ def test_params_without_loads_pick_the_coefficient_buffer_only():
         P.required_bytes(P.params_from_solve(s, loads=False))
 
 
-def test_diffuse_and_maxwell_boxes_keep_populations():
-    """A box with diffuse or Maxwell faces is kept as populations: two
-    population buffers, more than the coefficient state of a bounce-back box
-    of the same size."""
+def test_diffuse_and_maxwell_boxes_in_both_representations():
+    """A box with diffuse or Maxwell faces is kept like a bounce-back one:
+    as coefficients by default (the face tables add a few hundred kB), as
+    populations on request."""
     cells = 128 * 128
+    nbb = P.required_bytes(_box())
     for kw in ({"wall": B.WALL_DS}, {"wall": B.WALL_MAXWELL, "accommodation": 0.4}):
         n = P.required_bytes(_box(**kw))
-        assert n >= 2 * 37 * cells * 4
-    assert P.required_bytes(_box()) < 2 * 37 * cells * 4
+        assert nbb <= n < 2 * 37 * cells * 4
+        assert P.required_bytes(_box(representation=B.REPR_POPULATIONS, **kw)) >= \
+            2 * 37 * cells * 4
+        assert P.required_bytes(_box(representation=B.REPR_COEFFICIENTS_NOLOAD, **kw)) < \
+            16 * cells * 4
 
 
 def test_diffuse_and_maxwell_walls_on_a_plate_are_accepted():

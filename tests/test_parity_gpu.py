@@ -156,13 +156,16 @@ def test_small_parity_maxwell_wall(P, name, storage, repr_, sigma):
 
 
 @pytest.mark.parametrize("wall,sigma", [("ds", 1.0), ("maxwell", 0.0), ("maxwell", 0.6)])
+@pytest.mark.parametrize("repr_", [1, 2], ids=["populations", "coefficients"])
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
 @pytest.mark.parametrize("name", ["q9_box", "q37_box", "q37_box_bgk"])
-def test_small_parity_box_walls(P, name, storage, wall, sigma):
+def test_small_parity_box_walls(P, name, storage, repr_, wall, sigma):
     """Diffuse, specular and mixed faces on the box (faces cut into columns,
-    corner links bounce back; the box is kept as populations) against the
+    corner links bounce back) in both device representations against the
     oracle: populations after 40 steps, every per-step force, the impedance."""
-    _small_parity(P, name, storage, 1, wall=wall, sigma=sigma)
+    if repr_ == 2 and SMALL[name][3] != "regularized":
+        pytest.skip("coefficients hold only the regularized (H2) state")
+    _small_parity(P, name, storage, repr_, wall=wall, sigma=sigma)
 
 
 @pytest.mark.parametrize("wall,sigma", [("ds", 1.0), ("maxwell", 0.0), ("maxwell", 0.6)])
@@ -309,16 +312,17 @@ def _solve_from_golden(g, storage="f32dev"):
     return W.Solve(**d)
 
 
-def _batch_full(P, names):
-    """Run the stored workloads `names` (FP32 deviation storage, the
-    representation the library picks, from rest) as one batch; return the
-    (golden, solve, force history, impedance) of each."""
+def _batch_full(P, names, representation=0):
+    """Run the stored workloads `names` (FP32 deviation storage, from rest,
+    the representation the library picks unless one is given) as one batch;
+    return the (golden, solve, force history, impedance) of each."""
     import torch
     gs = [_golden(n) for n in names]
     solves = [_solve_from_golden(g) for g in gs]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        svs = [P.Solver(P.params_from_solve(s, loads=False), stream=stream) for s in solves]
+        svs = [P.Solver(P.params_from_solve(s, loads=False, representation=representation),
+                        stream=stream) for s in solves]
         b = P.Batch(stream)
         try:
             for sv, s in zip(svs, solves):
@@ -366,13 +370,15 @@ def test_wide_plates_full_in_batch(P):
 WALL_BOXES = ["wall_box_ds_tw1", "wall_box_maxwell0_tw1"]
 
 
-def test_wall_boxes_full_in_batch(P):
+@pytest.mark.parametrize("repr_", [1, 2], ids=["populations", "coefficients"])
+def test_wall_boxes_full_in_batch(P, repr_):
     """The 32 x 16 body in a 256^2 domain with diffuse and with specular
-    faces, tau*omega = 1, 20 480 steps, advanced as one batch in FP32:
-    impedance within T2 of the stored FP64 oracle runs, every stored force
-    sample within 1e-3 of the force scale, and no lift beyond rounding."""
-    for g, s, fx, z, repr_ in _batch_full(P, WALL_BOXES):
-        assert repr_ == P.lbm.REPR_POPULATIONS
+    faces, tau*omega = 1, 20 480 steps, advanced as one batch in FP32 in
+    either device representation: impedance within T2 of the stored FP64
+    oracle runs and every stored force sample within 1e-3 of the force
+    scale."""
+    for g, s, fx, z, got in _batch_full(P, WALL_BOXES, representation=repr_):
+        assert got == repr_
         _assert_t2(z, g, s.name)
         _cmp_samples(fx, g, 1e-3)
 
@@ -626,6 +632,12 @@ def test_batch_alone_equals_mix_with_diffuse_walls(P):
                 accommodation=0.6, name="wide_maxwell"),
         W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=90, ny=70, tau=0.9, omega=om,
                 box=(30, 25, 20, 12), nsteps=45, window_first=5, window_count=40, name="box"),
+        W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=80, ny=66, tau=0.8, omega=om,
+                box=(25, 20, 14, 9), nsteps=45, window_first=5, window_count=40, wall="ds",
+                name="box_ds"),
+        W.Solve(Q=37, geometry=W.BOX, far=W.FAR_EQ, nx=70, ny=60, tau=1.1, omega=om,
+                box=(22, 19, 11, 13), nsteps=45, window_first=5, window_count=40,
+                wall="maxwell", accommodation=0.3, name="box_maxwell"),
     ]
     ref = [_alone(P, s, stream) for s in solves]
     svs = [P.Solver(P.params_from_solve(s), stream=stream) for s in solves]
