@@ -170,10 +170,16 @@ def main(argv=None):
     ap.add_argument("--period", type=int, default=1024)
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
+    import time
     import torch
     torch.cuda.set_device(0)
-    recs = run_sweep(sweep_solves(period=a.period))
-    out = {"points": recs, "devices": device_curves(recs)}
+    pts = sweep_solves(period=a.period)
+    t0 = time.perf_counter()
+    recs = run_sweep(pts)
+    wall = time.perf_counter() - t0
+    out = {"points": recs, "devices": device_curves(recs),
+           "solves": len(pts), "wall_s": wall,
+           "glups": sum(s.fluid_cells * s.nsteps for s, _, _, _ in pts) / wall / 1e9}
     text = json.dumps(out)
     if a.json:
         with open(a.json, "w") as fh:
