@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -239,6 +240,8 @@ void mirror_of(const lbm_params* p, const HostLattice& L, int x, int y, int q, i
 struct ForceTables {
   std::vector<ForceLink> links;
   std::vector<ForceCell> cells;
+  std::vector<LinkWeights> lweights;
+  std::vector<CellWeights> cweights;
   double fstatic[2] = {0, 0}, kladd[2] = {0, 0};
   double ds[6] = {0, 0, 0, 0, 0, 0};
   // box with diffuse or Maxwell faces
@@ -375,15 +378,28 @@ void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout&
   const long double sigma = p->wall == LBM_WALL_MAXWELL ? (long double)p->accommodation : 1.0L;
   const long double mwx = diffuse ? sigma : 2.0L, mwy = diffuse ? 2.0L - sigma : 2.0L;
   std::unordered_map<int64_t, size_t> index;  // mirror cell -> position in t->cells
-  auto cell_for = [&](int px, int py) -> ForceCell& {
+  std::vector<CellWeights> cw;                 // the weights of t->cells
+  auto cell_for = [&](int px, int py) -> CellWeights& {
     const int64_t key = (int64_t)py * p->nx + px;
     auto it = index.find(key);
-    if (it != index.end()) return t->cells[it->second];
+    if (it != index.end()) return cw[it->second];
     ForceCell fc{};
     fc.off = (int64_t)py * lay.mpitch + px;
     index.emplace(key, t->cells.size());
     t->cells.push_back(fc);
-    return t->cells.back();
+    cw.push_back(CellWeights{});
+    return cw.back();
+  };
+  // one pattern per distinct set of weights (compared bit for bit)
+  std::unordered_map<std::string, int32_t> lpat, cpat;
+  auto pattern = [](auto& pats, auto& table, const auto& wts) {
+    const std::string key(reinterpret_cast<const char*>(&wts), sizeof(wts));
+    auto it = pats.find(key);
+    if (it != pats.end()) return it->second;
+    const int32_t k = (int32_t)table.size();
+    table.push_back(wts);
+    pats.emplace(key, k);
+    return k;
   };
   int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
   if (p->geometry == LBM_GEOM_PLATE) {
@@ -407,10 +423,12 @@ void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout&
         }
         int px, py;
         mirror_of(p, L, x, y, q, &px, &py);
-        t->links.push_back(ForceLink{L.opp[q] * lay.qs + py * lay.ys + px, (double)(-mwx * vx),
-                                     (double)(-mwy * vy), diffuse ? 1.0 : 0.0});
+        const LinkWeights lwt{(double)(-mwx * vx), (double)(-mwy * vy), diffuse ? 1.0 : 0.0,
+                              0.0};
+        t->links.push_back(ForceLink{L.opp[q] * lay.qs + py * lay.ys + px,
+                                     pattern(lpat, t->lweights, lwt), 0});
         if (lay.mom) {
-          ForceCell& fc = cell_for(px, py);
+          CellWeights& fc = cell_for(px, py);
           // basis of the opposite direction -v at the mirror cell
           const long double g[6] = {1, -(long double)vx, -(long double)vy,
                                     (long double)vx * vx, (long double)vx * vy,
@@ -423,6 +441,7 @@ void build_force_tables(const lbm_params* p, const HostLattice& L, const Layout&
         }
       }
     }
+  for (size_t i = 0; i < t->cells.size(); ++i) t->cells[i].pat = pattern(cpat, t->cweights, cw[i]);
   t->fstatic[0] = (double)sx;
   t->fstatic[1] = (double)sy;
   t->kladd[0] = (double)kx;
@@ -512,6 +531,10 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
   lay->nfcells = (int32_t)ft.cells.size();
   lay->off_links = take(sizeof(ForceLink) * ft.links.size());
   lay->off_fcells = take(sizeof(ForceCell) * ft.cells.size());
+  lay->nlweights = (int32_t)ft.lweights.size();
+  lay->ncweights = (int32_t)ft.cweights.size();
+  lay->off_lweights = take(sizeof(LinkWeights) * ft.lweights.size());
+  lay->off_cweights = take(sizeof(CellWeights) * ft.cweights.size());
   lay->nwcols = (int32_t)ft.wcols.size();
   lay->nwlinks = (int32_t)ft.wlinks.size();
   lay->off_wcols = take(sizeof(WallCol) * ft.wcols.size());
@@ -560,6 +583,8 @@ int init_solver(lbm_solver* s) {
   d.state = reinterpret_cast<SolveState*>(b + lay.off_state);
   d.links = reinterpret_cast<const ForceLink*>(b + lay.off_links);
   d.fcells = reinterpret_cast<const ForceCell*>(b + lay.off_fcells);
+  d.lweights = reinterpret_cast<const LinkWeights*>(b + lay.off_lweights);
+  d.cweights = reinterpret_cast<const CellWeights*>(b + lay.off_cweights);
   d.nlinks = lay.nlinks;
   if (lay.nwlinks > 0) {
     d.wcols = reinterpret_cast<const WallCol*>(b + lay.off_wcols);
@@ -645,6 +670,16 @@ int init_solver(lbm_solver* s) {
   if (!ft.cells.empty() &&
       (rc = hip_rc(hipMemcpyAsync(b + lay.off_fcells, ft.cells.data(),
                                   sizeof(ForceCell) * ft.cells.size(), hipMemcpyHostToDevice, st))))
+    return rc;
+  if (!ft.lweights.empty() &&
+      (rc = hip_rc(hipMemcpyAsync(b + lay.off_lweights, ft.lweights.data(),
+                                  sizeof(LinkWeights) * ft.lweights.size(), hipMemcpyHostToDevice,
+                                  st))))
+    return rc;
+  if (!ft.cweights.empty() &&
+      (rc = hip_rc(hipMemcpyAsync(b + lay.off_cweights, ft.cweights.data(),
+                                  sizeof(CellWeights) * ft.cweights.size(), hipMemcpyHostToDevice,
+                                  st))))
     return rc;
   if (!ft.wcols.empty() &&
       (rc = hip_rc(hipMemcpyAsync(b + lay.off_wcols, ft.wcols.data(),

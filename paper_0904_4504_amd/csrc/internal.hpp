@@ -39,8 +39,9 @@ struct HostLattice {
 struct Layout {
   int64_t pitch = 0, qs = 0, ys = 0, buf_elems = 0;
   int32_t ntiles = 0, cells_per_tile = kBlock, cpt = 1;
-  int32_t nlinks = 0, nfcells = 0, nwcols = 0, nwlinks = 0;
+  int32_t nlinks = 0, nfcells = 0, nwcols = 0, nwlinks = 0, nlweights = 0, ncweights = 0;
   uint64_t off_links = 0, off_fcells = 0, off_wcols = 0, off_wlinks = 0;
+  uint64_t off_lweights = 0, off_cweights = 0;
   // coefficient representation (mom): six coefficient planes, updated in
   // tiles of kCoefTileW columns x coef_tile_rows(coef_k) rows
   bool mom = false;

@@ -550,10 +550,11 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
     const S* __restrict__ c = static_cast<const S*>(d.mbuf[n & 1]);
     const int64_t ks = d.mks;
     for (int i = threadIdx.x; i < d.nfcells; i += kBlock) {
-      const ForceCell& fc = d.fcells[i];
+      const ForceCell& cell = d.fcells[i];
+      const CellWeights& fc = d.cweights[cell.pat];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const double v = (double)c[k * ks + fc.off];
+        const double v = (double)c[k * ks + cell.off];
         fx += fc.wx[k] * v;
         fy += fc.wy[k] * v;
         fm += fc.wm[k] * v;
@@ -563,8 +564,9 @@ __device__ void finalize_solve(const SolveDesc& d, int mode) {
     const S* __restrict__ f = static_cast<const S*>(n & 1 ? d.buf[1] : d.buf[0]);
 #pragma unroll 4
     for (int i = threadIdx.x; i < d.nlinks; i += kBlock) {
-      const ForceLink& l = d.links[i];
-      const double v = (double)f[l.off];
+      const ForceLink& link = d.links[i];
+      const LinkWeights& l = d.lweights[link.pat];
+      const double v = (double)f[link.off];
       fx += l.wx * v;
       fy += l.wy * v;
       fm += l.wm * v;

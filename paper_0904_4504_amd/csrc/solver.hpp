@@ -45,15 +45,23 @@ struct SolveState {
 // Momentum exchange of the wall force, precomputed per solve on the host.
 // Population state: F += (wx, wy) * buf[off] for every wall link (off = the
 // population at the mirror cell that crosses the wall), and M += wm * buf[off]
-// (the crossing mass, diffuse wall only).
+// (the crossing mass, diffuse wall only), the weights those of the link's
+// pattern (they depend on its direction only, so a solve has at most Q).
 struct ForceLink {
   int64_t off;
-  double wx, wy, wm;
+  int32_t pat, pad;
+};
+struct LinkWeights {
+  double wx, wy, wm, pad;
 };
 // Coefficient state: F += (wx . c, wy . c) and M += wm . c per mirror cell,
-// c_k = mbuf[k*mks + off] (the cell's links folded into 6-vectors).
+// c_k = mbuf[k*mks + off] (the cell's links folded into 6-vectors; cells with
+// the same set of links share one pattern of weights).
 struct ForceCell {
   int64_t off;
+  int32_t pat, pad;
+};
+struct CellWeights {
   double wx[6], wy[6], wm[6];
 };
 
@@ -102,6 +110,8 @@ struct SolveDesc {
   SolveState* state;
   const ForceLink* links;    // [nlinks]
   const ForceCell* fcells;   // [nfcells] (coefficient state only)
+  const LinkWeights* lweights;  // weight patterns of the links
+  const CellWeights* cweights;  // weight patterns of the cells
   void* mbuf[2];             // H2 coefficients (a0, bx, by, cxx, cxy, cyy) of the state, step
                              // n reads mbuf[n & 1]; coefficient k of cell (x, y) at
                              // k*mks + y*mys + x (null when the solver keeps populations)
