@@ -637,7 +637,7 @@ int init_solver(lbm_solver* s) {
   if (lay.mom) {
     std::vector<WorkItem> rest;
     order_coef_tiles(&mwork, &rest, 0, coef_wall_tiles(p, lay, s->lat.R), lay.mntiles,
-                     lay.tiles_x, 2 * lay.mbuf_bytes <= kBandedStateBytes);
+                     lay.tiles_x, 2 * lay.mbuf_bytes <= kCachedStateBytes);
     join_front(&mwork, rest);
     if ((int32_t)mwork.size() != lay.mnwork) return LBM_EINVAL;
   }
@@ -781,8 +781,8 @@ int launch_one_step(lbm_solver* s) {
                     s->stream);
     s->pop_pending = false;
   } else {
-    e = launch_coef(Q, f64, s->lay.coef_k, ds, s->d_desc, s->d_mwork, s->lay.mnwork, s->klat,
-                    s->stream);
+    e = launch_coef(Q, f64, s->lay.coef_k, ds, 2 * s->lay.mbuf_bytes > kCachedStateBytes,
+                    s->d_desc, s->d_mwork, s->lay.mnwork, s->klat, s->stream);
     mode = 1;
   }
   if (e != hipSuccess) return LBM_EHIP;

@@ -30,6 +30,8 @@ struct lbm_batch {
   // kernel (bounce-back wall, diffuse wall), coefficient kernel (the same);
   // every member runs the kernel instantiation it runs alone
   int ngroup[4] = {0, 0, 0, 0};
+  // coefficient groups whose state streams from HBM (nontemporal stores)
+  bool streaming[4] = {false, false, false, false};
   SolveDesc* d_descs = nullptr;
   WorkItem* d_work = nullptr;   // population-kernel items, then coefficient-kernel items
   int32_t* d_solves = nullptr;
@@ -95,7 +97,7 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
     if (lay.mom) {
       order_coef_tiles(&front[k], &group[k], (int32_t)i,
                        coef_wall_tiles(&act[i]->p, lay, act[i]->lat.R), lay.mntiles, lay.tiles_x,
-                       state[k] <= kBandedStateBytes);
+                       state[k] <= kCachedStateBytes);
     } else {
       order_tiles(&group[k], (int32_t)i, lay.ntiles,
                   (act[i]->p.nx + lay.cells_per_tile - 1) / lay.cells_per_tile);
@@ -107,6 +109,7 @@ int refresh(lbm_batch* b, const std::vector<lbm_solver*>& act) {
       group[k].swap(front[k]);
     }
     b->ngroup[k] = (int)group[k].size();
+    b->streaming[k] = state[k] > kCachedStateBytes;
     work.insert(work.end(), group[k].begin(), group[k].end());
   }
   if (act.empty()) return LBM_OK;
@@ -165,8 +168,8 @@ int launch_one(lbm_batch* b) {
       const hipError_t e =
           k < 2 ? launch_step(b->Q, f64, bgk, ds, b->cpt, false, b->d_descs, work, n, lat,
                               b->stream, own)
-                : launch_coef(b->Q, f64, b->coef_k, ds, b->d_descs, work, n, lat, b->stream,
-                              own);
+                : launch_coef(b->Q, f64, b->coef_k, ds, b->streaming[k], b->d_descs, work, n,
+                              lat, b->stream, own);
       if (e != hipSuccess) return e;
       work += n;
     }

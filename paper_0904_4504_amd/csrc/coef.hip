@@ -342,6 +342,19 @@ __device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
+// Store bypassing the caches' retention (the nontemporal policy bit): a
+// separate instruction form from a plain store, which the compiler cannot
+// merge with one.
+template <typename S>
+__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, S v) {
+  if constexpr (sizeof(S) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 2);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t, v),
+        r, off, 0, 2);
+}
+
 // An offset past the end of every plane (planes are below 2 GiB).
 constexpr uint32_t kNoCell = 0x80000000u;
 
@@ -653,7 +666,8 @@ __device__ __forceinline__ void compute_tile(const SolveDesc& d, const TileCtx<S
 // and the fluid: bit k of `valid` for row k).
 template <class L, typename S, int RB>
 __device__ __forceinline__ void store_tile(const SolveDesc& d, const TileCtx<S>& t, int tile,
-                                           int tid, const S (&res)[RB][6], uint32_t valid) {
+                                           int tid, const S (&res)[RB][6], uint32_t valid,
+                                           bool streaming) {
   using T = CoefTile<L, RB>;
   const gptr<S> mout = as_global(t.mout);
   const int64_t ks = d.mks;
@@ -661,6 +675,11 @@ __device__ __forceinline__ void store_tile(const SolveDesc& d, const TileCtx<S>&
   gptr<S> pout[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) pout[k] = scalar_ptr(mout + k * ks);
+  // the same planes as buffer resources, for the nontemporal stores
+  const uint32_t bytes = (uint32_t)d.ny * (uint32_t)ys * (uint32_t)sizeof(S);
+  __amdgpu_buffer_rsrc_t ro[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ro[k] = plane_rsrc(t.mout + k * ks, bytes);
   const int x = (tile % d.tiles_x) * kCoefTileW + (tid & 63);
   const int yb = (tile / d.tiles_x) * T::TH + (tid >> 6) * RB;
 #pragma unroll
@@ -668,11 +687,17 @@ __device__ __forceinline__ void store_tile(const SolveDesc& d, const TileCtx<S>&
     if (!(valid & (1u << k))) continue;
     const int y = yb + k;
     const uint32_t o = (uint32_t)(y * ys + x) * (uint32_t)sizeof(S);
-    // plain (cached) stores: the next step reads these planes back, and a
-    // state of 48 B per cell stays in the last-level cache between steps
-    // (nontemporal stores: 52.3 against 50.9 us per launch on the beam box)
+    // a state that stays in the last-level cache between steps is stored
+    // through it (the next step reads it back from there: 36.7 against
+    // 43.3 us per beam-box launch); a state streaming from HBM bypasses it
+    // (2.84 against 3.03 ms per launch of the 256-solve batch)
+    if (streaming) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) *at(pout[j], o) = res[k][j];
+      for (int j = 0; j < 6; ++j) buf_store_nt(ro[j], o, res[k][j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) *at(pout[j], o) = res[k][j];
+    }
   }
 }
 
@@ -705,7 +730,8 @@ __device__ __forceinline__ void stage_store(Pair<S>* C, const S (&c)[CoefTile<L,
 template <class L, typename S, int RB, bool DSW>
 __global__ __launch_bounds__(64 * kCoefWaves) void coef_kernel(const SolveDesc* __restrict__ descs,
                                                    const WorkItem* __restrict__ work,
-                                                   KernelLattice lat, CoefConst<S> cc) {
+                                                   KernelLattice lat, CoefConst<S> cc,
+                                                   int streaming) {
   using T = CoefTile<L, RB>;
   // staged row r, pair j, column c at C[(3 r + j) HW + c]: the reads of a
   // pair are 64-bit (128-bit) loads at consecutive lanes
@@ -732,47 +758,50 @@ __global__ __launch_bounds__(64 * kCoefWaves) void coef_kernel(const SolveDesc* 
   S res[RB][6];
   uint32_t valid = 0;
   compute_tile<L, S, RB, DSW>(d, ctx, wi.tile, C, lat, cc, tid, res, valid, U);
-  store_tile<L, S, RB>(d, ctx, wi.tile, tid, res, valid);
+  store_tile<L, S, RB>(d, ctx, wi.tile, tid, res, valid, streaming != 0);
 }
 
 template <class L, typename S, int RB>
-static hipError_t launch_rb(bool ds, const SolveDesc* descs, const WorkItem* work, int nwork,
-                            const KernelLattice& lat, hipStream_t stream,
+static hipError_t launch_rb(bool ds, bool streaming, const SolveDesc* descs, const WorkItem* work,
+                            int nwork, const KernelLattice& lat, hipStream_t stream,
                             const KernelEvents& ev) {
   const CoefConst<S> cc = coef_const<S>(lat);
   const dim3 grid(nwork), block(64 * kCoefWaves);
+  const int st = streaming ? 1 : 0;
   if (ds)
-    launch_kernel(coef_kernel<L, S, RB, true>, grid, block, stream, ev, descs, work, lat, cc);
+    launch_kernel(coef_kernel<L, S, RB, true>, grid, block, stream, ev, descs, work, lat, cc, st);
   else
-    launch_kernel(coef_kernel<L, S, RB, false>, grid, block, stream, ev, descs, work, lat, cc);
+    launch_kernel(coef_kernel<L, S, RB, false>, grid, block, stream, ev, descs, work, lat, cc, st);
   return hipGetLastError();
 }
 
 template <class L, typename S>
-static hipError_t launch_coef_t(int k, bool ds, const SolveDesc* descs, const WorkItem* work,
-                                int nwork, const KernelLattice& lat, hipStream_t stream,
-                                const KernelEvents& ev) {
+static hipError_t launch_coef_t(int k, bool ds, bool streaming, const SolveDesc* descs,
+                                const WorkItem* work, int nwork, const KernelLattice& lat,
+                                hipStream_t stream, const KernelEvents& ev) {
   switch (k) {
     case 1:
-      return launch_rb<L, S, 1>(ds, descs, work, nwork, lat, stream, ev);
+      return launch_rb<L, S, 1>(ds, streaming, descs, work, nwork, lat, stream, ev);
     case 2:
-      return launch_rb<L, S, 2>(ds, descs, work, nwork, lat, stream, ev);
+      return launch_rb<L, S, 2>(ds, streaming, descs, work, nwork, lat, stream, ev);
     case 3:
-      return launch_rb<L, S, 3>(ds, descs, work, nwork, lat, stream, ev);
+      return launch_rb<L, S, 3>(ds, streaming, descs, work, nwork, lat, stream, ev);
     default:
       return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_coef(int Q, bool f64, int k, bool ds, const SolveDesc* descs,
+hipError_t launch_coef(int Q, bool f64, int k, bool ds, bool streaming, const SolveDesc* descs,
                        const WorkItem* work, int nwork, const KernelLattice& lat,
                        hipStream_t stream, KernelEvents ev) {
   if (nwork <= 0) return hipSuccess;
   if (Q == 9)
-    return f64 ? launch_coef_t<D2Q9, double>(k, ds, descs, work, nwork, lat, stream, ev)
-               : launch_coef_t<D2Q9, float>(k, ds, descs, work, nwork, lat, stream, ev);
-  return f64 ? launch_coef_t<D2Q37, double>(k, ds, descs, work, nwork, lat, stream, ev)
-             : launch_coef_t<D2Q37, float>(k, ds, descs, work, nwork, lat, stream, ev);
+    return f64 ? launch_coef_t<D2Q9, double>(k, ds, streaming, descs, work, nwork, lat, stream,
+                                             ev)
+               : launch_coef_t<D2Q9, float>(k, ds, streaming, descs, work, nwork, lat, stream,
+                                            ev);
+  return f64 ? launch_coef_t<D2Q37, double>(k, ds, streaming, descs, work, nwork, lat, stream, ev)
+             : launch_coef_t<D2Q37, float>(k, ds, streaming, descs, work, nwork, lat, stream, ev);
 }
 
 }  // namespace lbm

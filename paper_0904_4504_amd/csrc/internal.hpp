@@ -15,8 +15,10 @@ namespace lbm {
 hipError_t launch_step(int Q, bool f64, bool bgk, bool ds, int cpt, bool outm,
                        const SolveDesc* descs, const WorkItem* work, int nwork,
                        const KernelLattice& lat, hipStream_t stream, KernelEvents ev = {});
-// ds: some solve of the launch has a diffuse-scattering wall.
-hipError_t launch_coef(int Q, bool f64, int k, bool ds, const SolveDesc* descs,
+// ds: some solve of the launch has a diffuse-scattering wall.  streaming:
+// the launch's state exceeds what stays in the last-level cache between
+// steps (its new coefficients then go out with nontemporal stores).
+hipError_t launch_coef(int Q, bool f64, int k, bool ds, bool streaming, const SolveDesc* descs,
                        const WorkItem* work, int nwork, const KernelLattice& lat,
                        hipStream_t stream, KernelEvents ev = {});
 hipError_t launch_finalize(bool f64, const SolveDesc* descs, const int32_t* solves, int nsolves,
@@ -73,11 +75,12 @@ std::vector<char> coef_wall_tiles(const lbm_params* p, const Layout& lay, int R)
 void order_coef_tiles(std::vector<WorkItem>* front, std::vector<WorkItem>* rest, int32_t solve,
                       const std::vector<char>& wall, int32_t ntiles, int32_t span, bool banded);
 // Coefficient launches whose two state buffers together take at most this
-// many bytes stay in the 256 MB last-level cache between steps; their tiles
-// go in bands (reuse of the halo rows within an XCD's L2), larger ones in the
-// row-interleaved order (adjacent rows in flight on all XCDs at once, the
-// better pattern when the state streams from HBM).
-constexpr uint64_t kBandedStateBytes = (uint64_t)192 << 20;
+// many bytes stay in the 256 MB last-level cache between steps: their tiles
+// go in bands (reuse of the halo rows within an XCD's L2) and their stores
+// are plain, so the next step reads the state from the cache.  Larger ones
+// stream from HBM: the row-interleaved order (adjacent rows in flight on all
+// XCDs at once) and nontemporal stores.
+constexpr uint64_t kCachedStateBytes = (uint64_t)192 << 20;
 // front, padded with no-ops to a multiple of 8 items, then rest.
 void join_front(std::vector<WorkItem>* front, const std::vector<WorkItem>& rest);
 
