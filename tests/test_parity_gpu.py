@@ -202,6 +202,18 @@ def test_small_parity_coef_tiles(P, name, storage, tile):
     _small_parity(P, name, storage, 2, tile)
 
 
+@pytest.mark.parametrize("wall,sigma", [("ds", 1.0), ("maxwell", 0.4)])
+@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("name", ["q9_box", "q37_box", "q37_plate_eq_wide"])
+def test_small_parity_coef_tiles_walls(P, name, storage, tile, wall, sigma):
+    """The diffuse and Maxwell walls (plate and box faces) in the coefficient
+    kernel's other tile shapes (1 and 2 cells per thread: every wall cell then
+    sits at another place of its tile and of the staged halo) against the
+    oracle."""
+    _small_parity(P, name, storage, 2, tile, wall=wall, sigma=sigma)
+
+
 @pytest.mark.parametrize("wall", ["bb", "ds", "maxwell"])
 @pytest.mark.parametrize("Q", [9, 37])
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
