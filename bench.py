@@ -407,6 +407,11 @@ def main():
         tflops = flops * cells / avg_kernel_s / 1e12
         roofline["alu"] = {"achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": tflops / FP32_VALU_PEAK_TFLOPS, "flops_per_update": flops}
+        # the same updates on the Q populations (2 Q s bytes each): the HBM
+        # rate a population kernel would need to match this one
+        pop_gbs = 2 * Q * 4 * cells / avg_kernel_s / 1e9
+        roofline["population_form"] = {"bytes_per_update": 2 * Q * 4, "equivalent": pop_gbs,
+                                       "unit": "GB/s", "over_peak": pop_gbs / HBM_PEAK_GBS}
     roofline.update({"kernel": kernel, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches,
                      "kernel_timing": "start and stop events recorded by each launch itself "
                                       "(extended launch), a second pass of the same number of "
