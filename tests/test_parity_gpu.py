@@ -508,6 +508,43 @@ def test_range_errors_and_history_ring(P):
             sv.step(1)
 
 
+def test_degenerate_calls(P):
+    """Zero steps, read-outs before any step, an empty batch, and a batch
+    stepped past its only member's last step: no-ops or range errors, and the
+    member's forces are those of the same solve stepped alone."""
+    import torch
+    s = _small_solve("q37_box", "f32dev", nsteps=12)
+    alone = _gpu(P, s)[0]
+    stream = torch.cuda.Stream()
+    with P.Solver(P.params_from_solve(s), stream=stream) as sv:
+        sv.step(0)
+        assert sv.steps_done == 0
+        with pytest.raises(P.LbmError) as e:
+            sv.impedance()
+        assert e.value.code == -4
+        with pytest.raises(P.LbmError) as e:
+            sv.force_history(0, 1)
+        assert e.value.code == -4
+        assert sv.force_history(0, 0)[0].size == 0
+        with P.Batch(stream) as b:
+            b.step(5)                 # no members
+            b.synchronize()
+            assert b.size() == (0, 0)
+            b.add(sv)
+            b.step(0)
+            b.step(12)
+            b.step(7)                 # the member is done: nothing more runs
+            b.synchronize()
+            assert b.size() == (1, 0)
+            assert sv.steps_done == 12
+            fx, _ = sv.force_history(0, 12)
+            b.remove(sv)
+        assert np.array_equal(fx, alone)
+        with pytest.raises(P.LbmError) as e:
+            sv.step(1)
+        assert e.value.code == -4
+
+
 def test_lockin_sums_match_force_series(P):
     s = _small_solve("q37_box", "f64", nsteps=60)
     p = P.params_from_solve(s)
