@@ -10,7 +10,8 @@ steps plus the last 64 steps in full.
   python tests/golden/make_golden.py beam_box [tw ...]     # D2Q37 1024^2 box, hours
   python tests/golden/make_golden.py batch_subsample       # seeded 4 of the 256-solve batch
   python tests/golden/make_golden.py wide_plate            # 64x2048 plates, tau*omega 0.01, 100
-  python tests/golden/make_golden.py wall_box              # 256^2 box, diffuse and specular faces
+  python tests/golden/make_golden.py wall_box              # 256^2 box, diffuse and specular faces,
+                                                           # tau*omega 0.01, 1, 100
   options: --threads N
 
 The batch subsample runs each drawn solve for its full 20 480 steps, except
@@ -113,7 +114,7 @@ def main():
                 s = W.wide_plate(tw, far, storage="f64")
                 write(s.name, run_case(s, "f64", a.threads, 97))
     elif a.case == "wall_box":
-        for tw in a.tau_omega or (1.0,):
+        for tw in a.tau_omega or (0.01, 1.0, 100.0):
             for wall, sigma in (("ds", 1.0), ("maxwell", 0.0)):
                 s = W.wall_box(tw, wall, sigma, storage="f64")
                 write(s.name, run_case(s, "f64", a.threads, 97))

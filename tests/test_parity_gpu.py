@@ -379,15 +379,15 @@ def test_wide_plates_full_in_batch(P):
         _cmp_samples(fx, g, 1e-3)
 
 
-WALL_BOXES = ["wall_box_ds_tw1", "wall_box_maxwell0_tw1"]
+WALL_BOXES = [f"wall_box_{w}_tw{tw}" for tw in ("0.01", "1", "100") for w in ("ds", "maxwell0")]
 
 
 @pytest.mark.parametrize("repr_", [1, 2], ids=["populations", "coefficients"])
 def test_wall_boxes_full_in_batch(P, repr_):
     """The 32 x 16 body in a 256^2 domain with diffuse and with specular
-    faces, tau*omega = 1, 20 480 steps, advanced as one batch in FP32 in
-    either device representation: impedance within T2 of the stored FP64
-    oracle runs and every stored force sample within 1e-3 of the force
+    faces, tau*omega = 0.01, 1 and 100, 20 480 steps, advanced as one batch in
+    FP32 in either device representation: impedance within T2 of the stored
+    FP64 oracle runs and every stored force sample within 1e-3 of the force
     scale."""
     for g, s, fx, z, got in _batch_full(P, WALL_BOXES, representation=repr_):
         assert got == repr_
