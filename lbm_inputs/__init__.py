@@ -209,16 +209,19 @@ def batch_parity_subsample(seed=40, count=256):
 
 
 def wide_plate(tau_omega, far, nx=64, ny=2048, period=1024, transient_periods=10,
-               window_periods=10, storage="f32dev"):
+               window_periods=10, storage="f32dev", wall="bb", accommodation=1.0):
     """D2Q37 plate wide enough (nx >= 64) to be kept as H2 coefficients, with
     the stationary far wall (far=FAR_WALL) or the rest-equilibrium far field
-    (far=FAR_EQ): the plates of the batch sweep run this way."""
+    (far=FAR_EQ): the plates of the batch sweep run this way.  wall: the
+    moving wall's model ("bb", "ds" or "maxwell" with its accommodation)."""
     omega = 2 * math.pi / period
     steps = (transient_periods + window_periods) * period
+    tag = "" if wall == "bb" else ("ds_" if wall == "ds" else f"{wall}{accommodation:g}_")
     return Solve(Q=37, geometry=PLATE, far=far, nx=nx, ny=ny, tau=tau_lb(tau_omega, omega),
                  omega=omega, nsteps=steps, window_first=transient_periods * period,
                  window_count=window_periods * period, storage=storage, tau_omega=tau_omega,
-                 name=f"wide_plate_{far}_tw{tau_omega:g}")
+                 wall=wall, accommodation=accommodation,
+                 name=f"wide_plate_{far}_{tag}tw{tau_omega:g}")
 
 
 # --------------------------------------------------------------- noise

@@ -10,6 +10,7 @@ steps plus the last 64 steps in full.
   python tests/golden/make_golden.py beam_box [tw ...]     # D2Q37 1024^2 box, hours
   python tests/golden/make_golden.py batch_subsample       # seeded 4 of the 256-solve batch
   python tests/golden/make_golden.py wide_plate            # 64x2048 plates, tau*omega 0.01, 100
+  python tests/golden/make_golden.py wide_plate_walls      # the same with diffuse, Maxwell walls
   python tests/golden/make_golden.py wall_box              # 256^2 box, diffuse and specular faces,
                                                            # tau*omega 0.01, 1, 100
   options: --threads N
@@ -86,7 +87,7 @@ def write(name, obj):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("case", choices=["stokes_plate", "plate_sweep", "beam_box", "batch_subsample",
-                                     "wide_plate", "wall_box"])
+                                     "wide_plate", "wide_plate_walls", "wall_box"])
     ap.add_argument("tau_omega", nargs="*", type=float)
     ap.add_argument("--threads", type=int, default=0)
     a = ap.parse_args()
@@ -112,6 +113,11 @@ def main():
         for far in (W.FAR_WALL, W.FAR_EQ):
             for tw in a.tau_omega or (0.01, 100.0):
                 s = W.wide_plate(tw, far, storage="f64")
+                write(s.name, run_case(s, "f64", a.threads, 97))
+    elif a.case == "wide_plate_walls":
+        for tw in a.tau_omega or (0.01, 100.0):
+            for wall, sigma in (("ds", 1.0), ("maxwell", 0.6)):
+                s = W.wide_plate(tw, W.FAR_EQ, storage="f64", wall=wall, accommodation=sigma)
                 write(s.name, run_case(s, "f64", a.threads, 97))
     elif a.case == "wall_box":
         for tw in a.tau_omega or (0.01, 1.0, 100.0):

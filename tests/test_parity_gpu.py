@@ -365,6 +365,7 @@ def _assert_t2(z, g, name):
 
 
 WIDE_PLATES = [f"wide_plate_{far}_tw{tw:g}" for far in ("wall", "eq") for tw in (0.01, 100.0)]
+WALL_PLATES = [f"wide_plate_eq_{w}_tw{tw:g}" for w in ("ds", "maxwell0.6") for tw in (0.01, 100.0)]
 
 
 def test_wide_plates_full_in_batch(P):
@@ -375,6 +376,19 @@ def test_wide_plates_full_in_batch(P):
     every stored force sample within 1e-3 of the force scale."""
     for g, s, fx, z, repr_ in _batch_full(P, WIDE_PLATES):
         assert repr_ == P.lbm.REPR_COEFFICIENTS
+        _assert_t2(z, g, s.name)
+        _cmp_samples(fx, g, 1e-3)
+
+
+@pytest.mark.parametrize("repr_", [1, 2], ids=["populations", "coefficients"])
+def test_wall_plates_full_in_batch(P, repr_):
+    """The 64 x 2048 plate with the diffuse wall and with the Maxwell wall of
+    accommodation 0.6 (rest-equilibrium far field) at tau*omega = 0.01 and
+    100, 20 480 steps, advanced as one batch in FP32 in either device
+    representation: impedance within T2 of the stored FP64 oracle runs and
+    every stored force sample within 1e-3 of the force scale."""
+    for g, s, fx, z, got in _batch_full(P, WALL_PLATES, representation=repr_):
+        assert got == repr_
         _assert_t2(z, g, s.name)
         _cmp_samples(fx, g, 1e-3)
 
