@@ -26,10 +26,11 @@
 // stationary far wall arrives as zero; the lane of a cell within R of a wall
 // then adds the bounce-back value f_opp(x_p) + 2 w_i rho0 (v_i.U_w)/theta
 // (moving wall only), x_p the half-way mirror cell of the link (the rules of
-// the population kernel), read from the step's input state; at a plate with
-// the diffuse or the Maxwell wall it adds the diffuse emission (eq. DS),
-// mixed with the specular image for the Maxwell wall.  The finalize kernel
-// sums the momentum exchange from the same input state.
+// the population kernel), read from the step's input state; at a plate or a
+// box face with the diffuse or the Maxwell wall it adds the diffuse emission
+// (eq. DS) of the link's wall column, mixed with the specular image for the
+// Maxwell wall.  The finalize kernel sums the momentum exchange from the same
+// input state.
 #include <hip/hip_runtime.h>
 
 #include "device_util.hpp"
