@@ -495,9 +495,23 @@ void make_layout(const lbm_params* p, const HostLattice& L, Layout* lay) {
     const int th = coef_tile_rows(lay->coef_k);
     lay->tiles_x = (p->nx + kCoefTileW - 1) / kCoefTileW;
     lay->mntiles = lay->tiles_x * ((p->ny + th - 1) / th);
-    lay->mpitch = (int64_t)align_up(p->nx, 64);
-    lay->mks = (int64_t)align_up((uint64_t)p->ny * lay->mpitch, 256) + 256;
-    lay->mbuf_bytes = 6 * (uint64_t)lay->mks * es;
+    // element (k, y, x) of a buffer at k*mks + y*mpitch + x.  Row-interleaved
+    // where the whole buffer stays addressable with 32-bit byte offsets: the
+    // six coefficient rows of lattice row y side by side, so the staged rows
+    // and the stores of a tile fall in one contiguous span (2 % faster on a
+    // state streaming from HBM than six whole planes).  Larger lattices keep
+    // six planes, each under 2 GiB, spaced 256 elements past a 256-element
+    // boundary.
+    const int64_t pitch = (int64_t)align_up(p->nx, 64);
+    if ((uint64_t)p->ny * 6 * (uint64_t)pitch * es < ((uint64_t)1 << 31)) {
+      lay->mpitch = 6 * pitch;
+      lay->mks = pitch;
+      lay->mbuf_bytes = ((uint64_t)align_up((uint64_t)p->ny * lay->mpitch, 256) + 256) * es;
+    } else {
+      lay->mpitch = pitch;
+      lay->mks = (int64_t)align_up((uint64_t)p->ny * pitch, 256) + 256;
+      lay->mbuf_bytes = 6 * (uint64_t)lay->mks * es;
+    }
   }
   const int64_t ncells = (int64_t)p->nx * p->ny;
   // the coefficient solver's population kernel (first step after a load)
@@ -1088,7 +1102,7 @@ struct StateHeader {
   int32_t nx, ny;
   uint64_t bytes;
 };
-constexpr uint32_t kStateMagic = 0x4c424d31;  // "LBM1"
+constexpr uint32_t kStateMagic = 0x4c424d32;  // "LBM2": row-interleaved coefficient buffers
 
 uint64_t state_payload(const lbm_solver* s) {
   return (s->lay.mom && !s->pop_pending) ? s->lay.mbuf_bytes : s->lay.buf_bytes;

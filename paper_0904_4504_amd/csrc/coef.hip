@@ -356,7 +356,18 @@ __device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, uint32_t 
         r, off, 0, 2);
 }
 
-// An offset past the end of every plane (planes are below 2 GiB).
+// Extent of one coefficient plane's buffer resource: from its first element
+// to the last element of its last row.  Element (k, y, x) sits at
+// k*ks + y*ys + x: six whole planes (ks >= ny*ys) or, row-interleaved, the
+// six rows of a lattice row side by side (ks = row pitch, ys = 6 ks); either
+// way plane 5's resource ends inside the buffer.  The library keeps the
+// extent below 2 GiB.
+template <typename S>
+__device__ __forceinline__ uint32_t plane_bytes(int ny, int64_t ys, int64_t ks) {
+  return (uint32_t)(((int64_t)(ny - 1) * ys + (ks < ys ? ks : ys)) * (int64_t)sizeof(S));
+}
+
+// An offset past the end of every plane's resource (all below 2 GiB).
 constexpr uint32_t kNoCell = 0x80000000u;
 
 // Population that output row k pulls from the source cell at column offset
@@ -419,7 +430,7 @@ __device__ __forceinline__ void stage_load(const SolveDesc& d, const TileCtx<S>&
   const int nx = d.nx, ny = d.ny;
   const int64_t ks = d.mks;
   const int ys = (int)d.mys;
-  const uint32_t bytes = (uint32_t)ny * (uint32_t)ys * (uint32_t)sizeof(S);
+  const uint32_t bytes = plane_bytes<S>(ny, ys, ks);
   __amdgpu_buffer_rsrc_t rs[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) rs[k] = plane_rsrc(min + k * ks, bytes);
@@ -677,7 +688,7 @@ __device__ __forceinline__ void store_tile(const SolveDesc& d, const TileCtx<S>&
 #pragma unroll
   for (int k = 0; k < 6; ++k) pout[k] = scalar_ptr(mout + k * ks);
   // the same planes as buffer resources, for the nontemporal stores
-  const uint32_t bytes = (uint32_t)d.ny * (uint32_t)ys * (uint32_t)sizeof(S);
+  const uint32_t bytes = plane_bytes<S>(d.ny, ys, ks);
   __amdgpu_buffer_rsrc_t ro[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) ro[k] = plane_rsrc(t.mout + k * ks, bytes);

@@ -49,7 +49,7 @@ struct Layout {
   bool mom = false;
   bool loadable = true;  // has the population buffer a populations load needs
   int32_t coef_k = 0, tiles_x = 0, mntiles = 0;
-  int64_t mpitch = 0, mks = 0;
+  int64_t mpitch = 0, mks = 0;  // coefficient buffers: row and plane strides (elements)
   uint64_t mbuf_bytes = 0, off_mwork = 0, off_mbuf[2] = {0, 0};
   int32_t nwork = 0, mnwork = 0;  // population-kernel and coefficient-kernel work items
   int64_t hist_cap = 0;
