@@ -318,7 +318,19 @@ struct CoefTile {
   static constexpr int NT = 64 * kCoefWaves;  // threads
   static constexpr int TH = kCoefWaves * RB;  // tile rows
   static constexpr int HW = kCoefTileW + 2 * R, HH = TH + 2 * R, NC = HW * HH;
-  static constexpr int NIT = (NC + NT - 1) / NT;  // staged cells per thread
+  // staging: the 64 core cells of staged row r (columns R .. R + 63) are
+  // loaded by wavefront r mod 4, one cell per lane; the 2R halo cells of
+  // every staged row by the first NHALO threads
+  static constexpr int NCR = (HH + kCoefWaves - 1) / kCoefWaves;  // core rows per wave
+  static constexpr int NHALO = 2 * R * HH;
+  static constexpr int NHIT = (NHALO + NT - 1) / NT;  // halo cells per thread
+};
+
+// A thread's share of a staged tile between its loads and its LDS writes.
+template <class L, typename S, int RB>
+struct StageRegs {
+  S core[CoefTile<L, RB>::NCR][6];
+  S halo[CoefTile<L, RB>::NHIT][6];
 };
 
 namespace {
@@ -421,11 +433,17 @@ __device__ __forceinline__ TileCtx<S> tile_ctx(const SolveDesc& d) {
 
 // Load a tile's staged region (the tile and its R-cell halo) into registers:
 // body and outside cells as zeros, periodic images where the geometry wraps.
+// Each core load of a wavefront covers 64 consecutive cells of one row of one
+// coefficient, starting at a multiple of 64 cells: a tile's loads touch whole
+// aligned segments, and only the 2R halo cells per row come in separately
+// (a 70-cell row loaded lane by lane straddles rows at unaligned starts:
+// 11 % slower on the memory side of a state streaming from HBM).
 template <class L, typename S, int RB>
 __device__ __forceinline__ void stage_load(const SolveDesc& d, const TileCtx<S>& t, int tile,
-                                           S (&c)[CoefTile<L, RB>::NIT][6], int tid) {
+                                           StageRegs<L, S, RB>& g, int tid) {
   using T = CoefTile<L, RB>;
-  constexpr int R = T::R, HW = T::HW, NC = T::NC;
+  constexpr int R = T::R, HH = T::HH;
+  constexpr uint32_t es = sizeof(S);
   const S* min = t.min;
   const int nx = d.nx, ny = d.ny;
   const int64_t ks = d.mks;
@@ -436,42 +454,37 @@ __device__ __forceinline__ void stage_load(const SolveDesc& d, const TileCtx<S>&
   for (int k = 0; k < 6; ++k) rs[k] = plane_rsrc(min + k * ks, bytes);
   const int x0 = (tile % d.tiles_x) * kCoefTileW;
   const int y0 = (tile / d.tiles_x) * T::TH;
+  const int lane = tid & 63, wv = tid >> 6;
   const bool xper = d.geom != GEOM_BOX, yper = d.geom == GEOM_PERIODIC;
   const bool is_box = d.geom == GEOM_BOX;
   const int bx0 = d.bx0, bx1 = d.bx1, by0 = d.by0, by1 = d.by1;
-  // staged cell i = tid + NT it sits at (hx, hy) of the halo tile; step
-  // (hx, hy) instead of dividing per cell
-  constexpr int DX = T::NT % HW, DY = T::NT / HW;
-  int hx = tid % HW, hy = tid / HW;
-  // byte offsets of the staged cells first, then the loads (one code path,
-  // so the wait before each use covers exactly the loads it needs)
-  uint32_t o[T::NIT];
+  // byte offsets first, then the loads (one code path, so the wait before
+  // each use covers exactly the loads it needs)
+  uint32_t oc[T::NCR], oh[T::NHIT];
   // a staged region inside the lattice, clear of the body: every cell is
-  // read as is (cells past the region read past it, within or beyond the
-  // plane, and are not stored)
+  // read as is
   const bool inside = x0 >= R && x0 + kCoefTileW + R <= nx && y0 >= R && y0 + T::TH + R <= ny &&
                       !(is_box && x0 - R < bx1 && x0 + kCoefTileW + R > bx0 && y0 - R < by1 &&
                         y0 + T::TH + R > by0);
   if (inside) {
-    constexpr uint32_t es = sizeof(S);
-    uint32_t oi = (uint32_t)((y0 - R + hy) * ys + x0 - R + hx) * es;
-    const uint32_t step = (uint32_t)(DY * ys + DX) * es, wrap = (uint32_t)(ys - HW) * es;
+    uint32_t o = (uint32_t)((y0 - R + wv) * ys + x0 + lane) * es;
+    const uint32_t step = (uint32_t)(kCoefWaves * ys) * es;
 #pragma unroll
-    for (int it = 0; it < T::NIT; ++it) {
-      o[it] = oi;
-      oi += step;
-      hx += DX;
-      if (hx >= HW) {
-        hx -= HW;
-        oi += wrap;
-      }
+    for (int m = 0; m < T::NCR; ++m) {
+      // rows past the region (wave-uniform) read nothing and are not written
+      oc[m] = wv + kCoefWaves * m < HH ? o : kNoCell;
+      o += step;
+    }
+#pragma unroll
+    for (int it = 0; it < T::NHIT; ++it) {
+      const int i = tid + it * T::NT, j = i % (2 * R), hy = i / (2 * R);
+      const int hx = j < R ? j : kCoefTileW + j;
+      oh[it] = i < T::NHALO ? (uint32_t)((y0 - R + hy) * ys + x0 - R + hx) * es : kNoCell;
     }
   } else {
     // lattices narrower than the staged tile wrap more than once
-    const bool narrow = nx < HW || (yper && ny < T::HH);
-#pragma unroll
-    for (int it = 0; it < T::NIT; ++it) {
-      const int i = tid + it * T::NT;
+    const bool narrow = nx < T::HW || (yper && ny < HH);
+    auto offset = [&](int hx, int hy) -> uint32_t {
       int gx = x0 - R + hx, gy = y0 - R + hy;
       if (xper) {
         gx += gx < 0 ? nx : 0;
@@ -486,21 +499,29 @@ __device__ __forceinline__ void stage_load(const SolveDesc& d, const TileCtx<S>&
         if (yper) gy = (((y0 - R + hy) % ny) + ny) % ny;
       }
       const bool solid = is_box && gx >= bx0 && gx < bx1 && gy >= by0 && gy < by1;
-      const bool load = i < NC && gx >= 0 && gx < nx && gy >= 0 && gy < ny && !solid;
+      const bool load = gx >= 0 && gx < nx && gy >= 0 && gy < ny && !solid;
       // cells without data read past the end of the plane: zeros
-      o[it] = load ? (uint32_t)(gy * ys + gx) * (uint32_t)sizeof(S) : kNoCell;
-      hx += DX;
-      hy += DY;
-      if (hx >= HW) {
-        hx -= HW;
-        ++hy;
-      }
+      return load ? (uint32_t)(gy * ys + gx) * es : kNoCell;
+    };
+#pragma unroll
+    for (int m = 0; m < T::NCR; ++m) {
+      const int hy = wv + kCoefWaves * m;
+      oc[m] = hy < HH ? offset(R + lane, hy) : kNoCell;
+    }
+#pragma unroll
+    for (int it = 0; it < T::NHIT; ++it) {
+      const int i = tid + it * T::NT, j = i % (2 * R), hy = i / (2 * R);
+      oh[it] = i < T::NHALO ? offset(j < R ? j : kCoefTileW + j, hy) : kNoCell;
     }
   }
 #pragma unroll
-  for (int it = 0; it < T::NIT; ++it)
+  for (int m = 0; m < T::NCR; ++m)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) c[it][k] = buf_load<S>(rs[k], o[it]);
+    for (int k = 0; k < 6; ++k) g.core[m][k] = buf_load<S>(rs[k], oc[m]);
+#pragma unroll
+  for (int it = 0; it < T::NHIT; ++it)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g.halo[it][k] = buf_load<S>(rs[k], oh[it]);
 }
 
 // Moments, bounce-back corrections and collision of the RB cells of this
@@ -715,24 +736,26 @@ __device__ __forceinline__ void store_tile(const SolveDesc& d, const TileCtx<S>&
 
 // Write a loaded tile (stage_load) to LDS.
 template <class L, typename S, int RB>
-__device__ __forceinline__ void stage_store(Pair<S>* C, const S (&c)[CoefTile<L, RB>::NIT][6],
-                                            int tid) {
+__device__ __forceinline__ void stage_store(Pair<S>* C, const StageRegs<L, S, RB>& g, int tid) {
   using T = CoefTile<L, RB>;
-  // staged cell tid + NT it of the halo tile, at (hx, hy)
-  constexpr int DX = T::NT % T::HW, DY = T::NT / T::HW;
-  int hx = tid % T::HW, hy = tid / T::HW;
+  constexpr int R = T::R, HW = T::HW;
+  const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
-  for (int it = 0; it < T::NIT; ++it) {
-    if (tid + it * T::NT < T::NC)
+  for (int m = 0; m < T::NCR; ++m) {
+    const int hy = wv + kCoefWaves * m;
+    if (hy < T::HH)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
-        C[(hy * 3 + j) * T::HW + hx] = Pair<S>{c[it][2 * j], c[it][2 * j + 1]};
-    hx += DX;
-    hy += DY;
-    if (hx >= T::HW) {
-      hx -= T::HW;
-      ++hy;
-    }
+        C[(hy * 3 + j) * HW + R + lane] = Pair<S>{g.core[m][2 * j], g.core[m][2 * j + 1]};
+  }
+#pragma unroll
+  for (int it = 0; it < T::NHIT; ++it) {
+    const int i = tid + it * T::NT, jj = i % (2 * R), hy = i / (2 * R);
+    const int hx = jj < R ? jj : kCoefTileW + jj;
+    if (i < T::NHALO)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        C[(hy * 3 + j) * HW + hx] = Pair<S>{g.halo[it][2 * j], g.halo[it][2 * j + 1]};
   }
 }
 
@@ -762,9 +785,9 @@ __global__ __launch_bounds__(64 * kCoefWaves) void coef_kernel(const SolveDesc* 
   {
     // all loads of a thread are issued before the first LDS store, so the
     // block waits for one memory round trip, not one per staged cell
-    S c[T::NIT][6];
-    stage_load<L, S, RB>(d, ctx, wi.tile, c, tid);
-    stage_store<L, S, RB>(C, c, tid);
+    StageRegs<L, S, RB> g;
+    stage_load<L, S, RB>(d, ctx, wi.tile, g, tid);
+    stage_store<L, S, RB>(C, g, tid);
   }
   __syncthreads();
   S res[RB][6];
