@@ -77,6 +77,10 @@ SMALL = {
     "q37_box_bgk": (37, W.BOX, W.FAR_EQ, "bgk", 64, 40, (20, 14, 6, 5), 0.8),
     "q37_periodic": (37, W.PERIODIC, W.FAR_EQ, "regularized", 31, 37, (0, 0, 0, 0), 5.0),
     "q37_plate_large_tau": (37, W.PLATE, W.FAR_WALL, "regularized", 4, 260, (0, 0, 0, 0), 16298.0),
+    # periodic lattices shorter than a staged coefficient tile (18 rows for
+    # D2Q37, 14 for D2Q9): the staging wraps rows more than once
+    "q37_periodic_short": (37, W.PERIODIC, W.FAR_EQ, "regularized", 66, 11, (0, 0, 0, 0), 1.0),
+    "q9_periodic_short": (9, W.PERIODIC, W.FAR_EQ, "regularized", 64, 5, (0, 0, 0, 0), 0.8),
 }
 
 
@@ -195,7 +199,8 @@ def test_box_walls_free_molecular(P, Q, storage, wall, sigma):
 @pytest.mark.parametrize("tile", [1, 3])
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
 @pytest.mark.parametrize("name", ["q9_box", "q37_box", "q37_plate_eq_wide", "q37_periodic",
-                                  "q37_plate_wall_narrow"])
+                                  "q37_plate_wall_narrow", "q37_periodic_short",
+                                  "q9_periodic_short"])
 def test_small_parity_coef_tiles(P, name, storage, tile):
     """The coefficient kernel with its other tiles (1 and 3 cells per thread,
     tiles of 4 and 12 rows) against the oracle."""
