@@ -264,7 +264,9 @@ int lbm_set_deviations(lbm_solver* s, const double* host, uint64_t n);
 /* Raw device state (representation header + the current buffer), for
  * bit-exact checkpoints in either representation.  lbm_state_size gives the
  * byte count; lbm_set_state accepts only a blob taken from a solver with the
- * same parameters.  Both wait for the stream. */
+ * same parameters by a build with the same buffer layout (the header carries
+ * a layout tag; any other blob gives LBM_EINVAL).  Both wait for the
+ * stream. */
 int lbm_state_size(const lbm_solver* s, uint64_t* bytes);
 int lbm_get_state(lbm_solver* s, void* host, uint64_t bytes);
 int lbm_set_state(lbm_solver* s, const void* host, uint64_t bytes);
