@@ -7,7 +7,7 @@ per side, tau*omega log-uniform in [1e-2, 1e2], U0 = 1e-3, D2Q37, FP32
 deviation storage with FP64 force and lock-in), drawn from one seeded PCG64
 stream, advanced together as one batch with the tile the autotuner picks.
 Every member keeps its state as the six H2 coefficients per cell (48 B per
-update in FP32): 13 GB of state, 50 times the 256 MB last-level cache, so
+update in FP32): 13.5 GB of state, 53 times the 256 MB last-level cache, so
 every step streams it from HBM.  One step = one stream-collide launch over
 the tiles of all 256 lattices (pull advection of the 37 populations from the
 coefficients, bounce-back with the moving-wall term, moments, H2
@@ -24,6 +24,12 @@ Prints one JSON line: MLUPS (fluid-cell updates per second); the dominant
 kernel against its roofline (each launch of it records its own start and stop
 events over a second pass of K steps); and the CPU oracle timed on a bounded
 sample of the workload on this host, on all its cores and on one.
+
+The rate depends on the run's length: a short run (--steps 20) runs at the
+GPU's boost shader clock, while over about 600 steps of this streaming load
+the clock settles some 9 % lower under the board's power management and the
+batch step slows by as much (2.78 to 3.02 ms); the default 1000 + 1000 steps
+report that sustained rate.
 
     python bench.py [--steps K] [--warmup W] [--workload batch|beam_box|plate_sweep]
     python bench.py --workload batch_sweep   # sweep solves/s, batched vs plain loop
