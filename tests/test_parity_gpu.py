@@ -272,14 +272,18 @@ def _cmp_samples(fx, g, tol, key="fx"):
     return err
 
 
-def test_stokes_plate_full_fp64(P):
+@pytest.mark.parametrize("repr_", [0, 2], ids=["auto", "coefficients"])
+def test_stokes_plate_full_fp64(P, repr_):
     """D2Q9 FP64, 4 x 256, 160 850 steps with seeded noise: every sampled force
-    and the impedance within 1e-12 of the long-double oracle."""
+    and the impedance within 1e-12 of the long-double oracle, in the
+    representation the library picks (populations, for so narrow a lattice)
+    and in the H2 coefficients (the coefficient kernel's staging then wraps
+    each 4-cell row some 16 times)."""
     g = _golden("stokes_plate")["ld"]
     s = W.stokes_plate()
     v, w, th = P.lattice(9)
     f0 = w[:, None, None] * s.rho0 + W.initial_noise(s)
-    fx, fy, z, _ = _gpu(P, s, f0)
+    fx, fy, z, _ = _gpu(P, s, f0, repr_=repr_)
     _cmp_samples(fx, g, 1e-12)
     assert z["R"] == pytest.approx(g["fit"]["R"], rel=1e-12)
     assert z["X"] == pytest.approx(g["fit"]["X"], rel=1e-12)
@@ -287,16 +291,18 @@ def test_stokes_plate_full_fp64(P):
     assert abs(abs(z["Z"] / s.nx) / abs(Zs) - 1) < 1e-2
 
 
+@pytest.mark.parametrize("repr_", [0, 2], ids=["auto", "coefficients"])
 @pytest.mark.parametrize("tw", W.PLATE_SWEEP_TAU_OMEGA)
-def test_plate_sweep_full(P, tw):
+def test_plate_sweep_full(P, tw, repr_):
     """D2Q37, 4 x 2048, 30 periods: FP32-deviation storage within 1e-4 on |Z|
-    and 1e-4 rad on the phase of the FP64 oracle; FP64 storage within 1e-12."""
+    and 1e-4 rad on the phase of the FP64 oracle; FP64 storage within 1e-12;
+    in the representation the library picks and in the H2 coefficients."""
     g = _golden(f"plate_sweep_tw{tw:g}")
     Zo = complex(g["fit"]["R"], g["fit"]["X"])
     for storage in ("f32dev", "f64"):
         s = W.plate_sweep(tw, storage=storage)
-        fx, fy, z, _ = _gpu(P, s)
-        print(f"tw={tw} {storage} Z={z['Z']} oracle={Zo}", flush=True)
+        fx, fy, z, _ = _gpu(P, s, repr_=repr_)
+        print(f"tw={tw} {storage} repr {repr_} Z={z['Z']} oracle={Zo}", flush=True)
         if storage == "f64":
             assert abs(z["Z"] - Zo) <= 1e-12 * abs(Zo)
             _cmp_samples(fx, g, 1e-11)
