@@ -311,16 +311,18 @@ def test_plate_sweep_full(P, tw, repr_):
             assert abs(cmath.phase(z["Z"]) - cmath.phase(Zo)) <= 1e-4
 
 
+@pytest.mark.parametrize("repr_", [0, 1], ids=["auto", "populations"])
 @pytest.mark.parametrize("tw", W.BEAM_TAU_OMEGA)
-def test_beam_box_full(P, tw):
+def test_beam_box_full(P, tw, repr_):
     """D2Q37 FP32 deviation storage, 1024^2 with a 32 x 16 body, 20 480 steps:
     impedance within 1e-4 (|Z|) and 1e-4 rad of the FP64 oracle; the body is
-    y-symmetric so the lift stays at rounding level."""
+    y-symmetric so the lift stays at rounding level.  In the representation
+    the library picks (the H2 coefficients) and as populations."""
     g = _golden(f"beam_box_tw{tw:g}")
     Zo = complex(g["fit"]["R"], g["fit"]["X"])
     s = W.beam_box(tw)
-    fx, fy, z, _ = _gpu(P, s)
-    print(f"tw={tw} Z={z['Z']} oracle={Zo}", flush=True)
+    fx, fy, z, _ = _gpu(P, s, repr_=repr_)
+    print(f"tw={tw} repr {repr_} Z={z['Z']} oracle={Zo}", flush=True)
     assert abs(abs(z["Z"]) / abs(Zo) - 1) <= 1e-4
     assert abs(cmath.phase(z["Z"]) - cmath.phase(Zo)) <= 1e-4
     _cmp_samples(fx, g, 1e-3)
